@@ -1,0 +1,165 @@
+"""Per-node oracle of one time step, in pull form (test infrastructure only).
+
+A second implementation of the step of scheme.py that visits nodes one at a
+time with explicit index arithmetic instead of whole-array rolls and padding:
+
+  * streaming is a pull, f_i(x) = f_post_i(x - c_i) (Eq. pushLB read
+    backwards), with half-way bounce-back f_i(x) = f_post_opp(i)(x) when
+    x - c_i lies behind a wall (reading R11 of scheme.py);
+  * ghost nodes are resolved by mapping every coordinate through the
+    periodic wrap or the half-way mirror, and the ghost velocity and normal
+    get their reflection signs node by node.
+
+The local physics (density, forces, equilibria, regularisation, source) is the
+one of scheme.py, evaluated on single nodes.  Used on tiny grids to check the
+streaming and boundary indexing of scheme.py, and on sampled nodes of full-size
+problems where the whole-array oracle does not fit in memory.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import scheme
+from .lattice import C, CS2, OPP, Q as NQ, W
+
+PERIODIC = scheme.PERIODIC
+
+
+class PointOracle:
+    """Evaluates one step at chosen nodes from a full state held on the host."""
+
+    def __init__(self, st, prob):
+        self.st = st
+        self.prob = prob
+        self.n = (prob.nx, prob.ny, prob.nz)
+        self._cache = {}
+
+    # -- coordinates ---------------------------------------------------------
+    def _map(self, ax, i):
+        """Map coordinate i on axis ax into the domain.  Returns (index, mirrored)."""
+        n = self.n[ax]
+        if self.prob.bc[ax] == PERIODIC:
+            return i % n, False
+        if i < 0:
+            return -1 - i, True
+        if i >= n:
+            return 2 * n - 1 - i, True
+        return i, False
+
+    def _inside(self, ax, i):
+        return self.prob.bc[ax] == PERIODIC or 0 <= i < self.n[ax]
+
+    def phi_at(self, x, y, z):
+        xs = self._map(0, x)[0]
+        ys = self._map(1, y)[0]
+        zs = self._map(2, z)[0]
+        return self.st.phi[zs, ys, xs]
+
+    # -- node quantities at an in-domain node ---------------------------------
+    def node(self, x, y, z):
+        key = (x, y, z)
+        if key in self._cache:
+            return self._cache[key]
+        prob, st = self.prob, self.st
+        phi = st.phi[z, y, x]
+        gphi = np.zeros(3)
+        lap = 0.0
+        grho = np.zeros(3)
+        rho_c = scheme.density(phi, prob)
+        for i in range(NQ):
+            cx, cy, cz = (int(v) for v in C[i])
+            pn = self.phi_at(x + cx, y + cy, z + cz)
+            gphi += (W[i] / CS2) * pn * C[i]
+            lap += (2.0 * W[i] / CS2) * (pn - phi)
+            grho += (W[i] / CS2) * scheme.density(pn, prob) * C[i]
+        P = st.P[z, y, x]
+        J = st.J[:, z, y, x].copy()
+        Qt = st.Q[:, :, z, y, x].copy()
+        F = scheme.total_force(np.float64(phi), gphi, np.float64(lap), grho,
+                               np.float64(P), Qt, prob)
+        om = scheme.relaxation(scheme.viscosity(phi, prob))
+        fpost, u, A, a = scheme.collide(np.float64(P), J, Qt, F, rho_c, om)
+        mag = np.sqrt(np.sum(gphi ** 2))
+        res = dict(phi=phi, grad_phi=gphi, lap=lap, u=u, fpost=fpost,
+                   n=gphi / (mag + scheme.EPS_NORMAL))
+        self._cache[key] = res
+        return res
+
+    def flux_parts(self, x, y, z):
+        """(phi, u, n) at a node that may be a ghost, with reflection signs."""
+        xs, mx = self._map(0, x)
+        ys, my = self._map(1, y)
+        zs, mz = self._map(2, z)
+        q = self.node(xs, ys, zs)
+        crossed = (mx, my, mz)
+        u = q["u"] * (-1.0) ** sum(crossed)
+        n = q["n"] * np.array([-1.0 if m else 1.0 for m in crossed])
+        return q["phi"], u, n
+
+    # -- one step at one node -------------------------------------------------
+    def step_at(self, x, y, z):
+        """Returns (phi', P', J'(3), Q'(3x3)) at in-domain node (x, y, z)."""
+        prob = self.prob
+        own = self.node(x, y, z)
+        f = np.empty(NQ)
+        for i in range(NQ):
+            cx, cy, cz = (int(v) for v in C[i])
+            src = (x - cx, y - cy, z - cz)
+            if all(self._inside(ax, src[ax]) for ax in range(3)):
+                xs = self._map(0, src[0])[0]
+                ys = self._map(1, src[1])[0]
+                zs = self._map(2, src[2])[0]
+                f[i] = self.node(xs, ys, zs)["fpost"][i]
+            else:
+                f[i] = own["fpost"][OPP[i]]
+        P = f.sum()
+        J = C.T.astype(np.float64) @ f
+        Pi = np.einsum("i,ia,ib->ab", f, C.astype(np.float64), C.astype(np.float64))
+        Qn = Pi - CS2 * P * np.eye(3) - np.outer(J, J)
+
+        kac = 4.0 * prob.mobility / prob.width
+        div_adv = 0.0
+        div_sharp = 0.0
+        for i in range(NQ):
+            cx, cy, cz = (int(v) for v in C[i])
+            ph, u, n = self.flux_parts(x + cx, y + cy, z + cz)
+            div_adv += (W[i] / CS2) * ph * float(np.dot(u, C[i]))
+            div_sharp += (W[i] / CS2) * ph * (1.0 - ph) * float(np.dot(n, C[i]))
+        if prob.literal_advection:
+            adv = float(np.dot(own["u"], own["grad_phi"]))
+        else:
+            adv = div_adv
+        phi_new = own["phi"] - adv + prob.mobility * own["lap"] - kac * div_sharp
+        return phi_new, P, J, Qn
+
+
+def step_points(st, prob, points):
+    """One step evaluated at a list of (x, y, z) nodes.  Returns dict of arrays."""
+    po = PointOracle(st, prob)
+    out = dict(phi=[], P=[], J=[], Q=[])
+    for (x, y, z) in points:
+        phi, P, J, Qn = po.step_at(int(x), int(y), int(z))
+        out["phi"].append(phi)
+        out["P"].append(P)
+        out["J"].append(J)
+        out["Q"].append(Qn)
+    return {k: np.array(v) for k, v in out.items()}
+
+
+def step_full(st, prob):
+    """Whole-grid step by visiting every node (tiny grids only)."""
+    nz, ny, nx = st.phi.shape
+    po = PointOracle(st, prob)
+    phi = np.empty_like(st.phi)
+    P = np.empty_like(st.P)
+    J = np.empty_like(st.J)
+    Qt = np.empty_like(st.Q)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                a, b, c, d = po.step_at(x, y, z)
+                phi[z, y, x] = a
+                P[z, y, x] = b
+                J[:, z, y, x] = c
+                Qt[:, :, z, y, x] = d
+    return scheme.State(phi, P, J, Qt)

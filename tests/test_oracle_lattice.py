@@ -1,0 +1,184 @@
+"""Pins of the oracle's local formulas against closed forms.
+
+The Hermite equilibrium, the recursive non-equilibrium and the Guo source are
+defined (Sec. II.B) by the moments they must carry; the isotropic stencils
+(Sec. II.C) by their Fourier symbols and their exactness on polynomials.  Each
+test below fails on a dropped term, a wrong prefactor or sign, or a transposed
+index in the oracle.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import lattice as L
+from oracle import scheme as S
+from paper_2501_00846_amd.workloads import Problem
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+D = np.eye(3)
+
+
+def test_weights_and_isotropy():
+    c = L.C.astype(float)
+    assert L.W.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose(np.einsum("i,ia->a", L.W, c), 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib->ab", L.W, c, c), L.CS2 * D, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib,ig->abg", L.W, c, c, c), 0, atol=1e-16)
+    m4 = np.einsum("i,ia,ib,ig,id->abgd", L.W, c, c, c, c)
+    iso = L.CS2 ** 2 * (np.einsum("ab,gd->abgd", D, D) + np.einsum("ag,bd->abgd", D, D)
+                        + np.einsum("ad,bg->abgd", D, D))
+    assert np.allclose(m4, iso, atol=1e-16)
+    assert (L.C[L.OPP] == -L.C).all()
+    # the diagonal third-order Hermite component vanishes on every D3Q27 vector
+    for i in range(L.Q):
+        for a in range(3):
+            assert L.H3(i)[a, a, a] == 0.0
+
+
+def _rand(rng, n):
+    P = rng.uniform(-0.1, 0.1, n)
+    u = rng.uniform(-0.1, 0.1, (3, n))
+    A = rng.uniform(-0.01, 0.01, (3, 3, n))
+    A = 0.5 * (A + A.transpose(1, 0, 2))
+    a = rng.uniform(-1e-3, 1e-3, (3, n))
+    return P, u, A, a
+
+
+def _mom(f):
+    c = L.C.astype(float)
+    m0 = f.sum(0)
+    m1 = np.einsum("ia,i...->a...", c, f)
+    m2 = np.einsum("iab,i...->ab...", L.H2_ALL, f)
+    m3 = np.einsum("iabg,i...->abg...", L.H3_ALL, f)
+    return m0, m1, m2, m3
+
+
+def _offdiag3():
+    return [t for t in itertools.product(range(3), repeat=3) if not (t[0] == t[1] == t[2])]
+
+
+def test_equilibrium_moments():
+    """sum feq = p*, sum feq c = u, sum feq H2 = uu, sum feq H3 = uuu (non-diagonal)."""
+    P, u, A, a = _rand(np.random.default_rng(0), 17)
+    m0, m1, m2, m3 = _mom(S.f_eq(P, u))
+    assert np.allclose(m0, P, rtol=0, atol=1e-15)
+    assert np.allclose(m1, u, rtol=0, atol=1e-15)
+    assert np.allclose(m2, np.einsum("a...,b...->ab...", u, u), rtol=0, atol=1e-15)
+    uuu = np.einsum("a...,b...,g...->abg...", u, u, u)
+    for t in _offdiag3():
+        assert np.allclose(m3[t], uuu[t], rtol=0, atol=1e-16)
+    for k in range(3):
+        assert np.allclose(m3[k, k, k], 0.0, atol=1e-16)
+
+
+def test_nonequilibrium_moments():
+    """sum fneq = 0, sum fneq c = 0, sum fneq H2 = a2, sum fneq H3 = a3 (non-diagonal)."""
+    P, u, A, a = _rand(np.random.default_rng(1), 13)
+    m0, m1, m2, m3 = _mom(S.f_neq(A, u))
+    assert np.allclose(m0, 0, atol=1e-17)
+    assert np.allclose(m1, 0, atol=1e-17)
+    assert np.allclose(m2, A, rtol=0, atol=1e-17)
+    a3 = (np.einsum("a...,bg...->abg...", u, A) + np.einsum("b...,ag...->abg...", u, A)
+          + np.einsum("g...,ab...->abg...", u, A))
+    for t in _offdiag3():
+        assert np.allclose(m3[t], a3[t], rtol=0, atol=1e-17)
+
+
+def test_guo_source_moments():
+    """sum S = 0, sum S c = a, sum S c c = u a + a u."""
+    P, u, A, a = _rand(np.random.default_rng(2), 11)
+    Sv = S.guo_source(u, a)
+    c = L.C.astype(float)
+    assert np.allclose(Sv.sum(0), 0, atol=1e-18)
+    assert np.allclose(np.einsum("ia,i...->a...", c, Sv), a, rtol=0, atol=1e-18)
+    ua = np.einsum("a...,b...->ab...", u, a)
+    assert np.allclose(np.einsum("ia,ib,i...->ab...", c, c, Sv), ua + ua.transpose(1, 0, 2),
+                       rtol=0, atol=1e-18)
+
+
+def test_collide_moments_closed_form():
+    """Post-collision moments follow from the definitions:
+    sum f_post = p*, sum f_post c = u + a/2 = J + a,
+    a2 = Q + a a / 4 (closed form of Eq. hermite_neq2 with u = J + a/2),
+    sum H2 f_post = uu + (1-omega) a2 + (ua + au)/2."""
+    rng = np.random.default_rng(3)
+    n = 9
+    P = rng.uniform(-0.1, 0.1, n)
+    J = rng.uniform(-0.05, 0.05, (3, n))
+    Q = rng.uniform(-0.01, 0.01, (3, 3, n))
+    Q = 0.5 * (Q + Q.transpose(1, 0, 2))
+    F = rng.uniform(-1e-3, 1e-3, (3, n))
+    rho = rng.uniform(0.001, 1.0, n)
+    om = rng.uniform(0.5, 1.9, n)
+    fpost, u, A, a = S.collide(P, J, Q, F, rho, om)
+    assert np.allclose(a, F / rho, rtol=1e-15)
+    assert np.allclose(u, J + 0.5 * F / rho, rtol=0, atol=1e-16)
+    aa = np.einsum("a...,b...->ab...", a, a)
+    assert np.allclose(A, Q + 0.25 * aa, rtol=0, atol=1e-16)
+    m0, m1, m2, _ = _mom(fpost)
+    assert np.allclose(m0, P, atol=1e-15)
+    assert np.allclose(m1, J + a, atol=1e-15)
+    ua = np.einsum("a...,b...->ab...", u, a)
+    assert np.allclose(m2, np.einsum("a...,b...->ab...", u, u) + (1 - om) * A
+                       + 0.5 * (ua + ua.transpose(1, 0, 2)), atol=1e-15)
+
+
+def test_stencil_symbols():
+    """Plane waves: grad_a -> i sin(k_a) prod_{b!=a} m(k_b), lap -> 6(m m m - 1),
+    m(k) = 2/3 + cos(k)/3, on a periodic grid."""
+    nx, ny, nz = 8, 6, 10
+    prob = Problem(nx, ny, nz)
+    x, y, z = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    x, y, z = (v.transpose(2, 1, 0) for v in (x, y, z))
+    for (mx, my, mz) in [(1, 0, 0), (2, 1, 3), (3, 2, 1), (4, 3, 5)]:
+        k = np.array([2 * np.pi * mx / nx, 2 * np.pi * my / ny, 2 * np.pi * mz / nz])
+        th = k[0] * x + k[1] * y + k[2] * z
+        m = 2 / 3 + np.cos(k) / 3
+        f = np.cos(th)
+        fp = S.pad(f, prob, 1)
+        g = S.grad(fp, 1)
+        for a in range(3):
+            sym = np.sin(k[a]) * np.prod([m[b] for b in range(3) if b != a])
+            assert np.allclose(g[a], -sym * np.sin(th), atol=1e-14)
+        lap = S.laplacian(fp, 1)
+        assert np.allclose(lap, 6 * (m.prod() - 1) * f, atol=1e-14)
+
+
+def test_stencils_exact_on_quadratics():
+    """Gradient and Laplacian are exact on quadratic polynomials; the
+    divergence of a linear field is its trace."""
+    n = 7
+    z, y, x = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float),
+                          np.arange(n, dtype=float), indexing="ij")
+    f = 0.3 * x ** 2 + 2 * y ** 2 - 0.7 * z ** 2 + 1.1 * x * y - 0.4 * y * z + 0.9 * x * z + x - 3
+    g = S.grad(f, 1)
+    sl = (slice(1, -1),) * 3
+    assert np.allclose(g[0], (0.6 * x + 1.1 * y + 0.9 * z + 1)[sl], atol=1e-12)
+    assert np.allclose(g[1], (4 * y + 1.1 * x - 0.4 * z)[sl], atol=1e-12)
+    assert np.allclose(g[2], (-1.4 * z - 0.4 * y + 0.9 * x)[sl], atol=1e-12)
+    assert np.allclose(S.laplacian(f, 1), 0.6 + 4 - 1.4, atol=1e-12)
+    v = np.stack([2 * x + y, -3 * y + z, 0.5 * z + x])
+    assert np.allclose(S.divergence(v, 1), 2 - 3 + 0.5, atol=1e-12)
+
+
+def test_chemical_potential_zero_on_profile():
+    """The tanh profile of width W is the exact zero of mu with beta = 12 sigma/W,
+    kappa = 3 sigma W/2 (continuum check with the analytic second derivative);
+    it carries surface tension sigma = int kappa phi'^2 dx; and the Allen-Cahn
+    flux M phi' - (4M/W) phi(1-phi) vanishes on it."""
+    prob = Problem(1, 1, 1, sigma=0.013, width=5.0, mobility=0.03)
+    W = prob.width
+    d = np.linspace(-30, 30, 20001)
+    t = np.tanh(2 * d / W)
+    phi = 0.5 * (1 + t)
+    dphi = (1 / W) * (1 - t ** 2)
+    d2phi = -(4 / W ** 2) * t * (1 - t ** 2)
+    mu = S.chemical_potential(phi, d2phi, prob)
+    assert np.max(np.abs(mu)) < 1e-15
+    kappa = 1.5 * prob.sigma * W
+    sig = np.trapezoid(kappa * dphi ** 2, d)
+    assert sig == pytest.approx(prob.sigma, rel=1e-7)
+    ac = prob.mobility * dphi - (4 * prob.mobility / W) * phi * (1 - phi)
+    assert np.max(np.abs(ac)) < 1e-16
