@@ -1,0 +1,212 @@
+/*
+ * lbm.h - C ABI of liblbm.so: one MI355X (gfx950) time step of the
+ * thread-safe, high-order lattice Boltzmann solver coupled to a conservative
+ * Allen-Cahn phase field, for droplet and bubble flows at high density and
+ * viscosity contrast (Lauricella et al., arXiv 2501.00846).
+ *
+ * Physics (paper sections):
+ *   Sec. II.A  incompressible two-phase Navier-Stokes with the potential-form
+ *              surface force F^s = mu_phi grad(phi) (Eq. jaqminforce), and the
+ *              conservative Allen-Cahn equation for phi in [0, 1], stepped by
+ *              FTCS on the same grid.
+ *   Sec. II.B  D3Q27 lattice, third-order Hermite equilibrium (Eq. eqts),
+ *              recursively regularised non-equilibrium (Eq. noneqts), Guo
+ *              source (Eq. guoforce); fused stream-and-collide from moments
+ *              only (Eq. pushLB), so no population array is stored.
+ *   Sec. II.C  force split F = F^s + F^p + F^nu (Eqs. press_corr,
+ *              visc_corr), rho = rho_l phi + (1 - phi) rho_g, isotropic FD
+ *              gradient and Laplacian.
+ *   Sec. II.D  the four phases of one step.
+ *   Sec. III   body force on the light phase, no-slip walls with a
+ *              neutral-wetting (Robin) phase-field condition.
+ *
+ * Conventions for every host array passed through this ABI:
+ *   - C order with x fastest: node index n = x + nx*(y + ny*z);
+ *   - vectors are three SoA planes (x plane, then y, then z), 3*N doubles;
+ *   - host arrays are owned by the caller and only read/written during the call.
+ * Lattice units throughout: dx = dt = 1, c_s^2 = 1/3.
+ *
+ * State per node (11 scalars, the thread-safe moment set):
+ *   phi, P = p* (= sum f), J = sum f c (3), Q = sum f (c c - c_s^2 I) - J J (6,
+ *   ordered xx, yy, zz, xy, xz, yz).  Velocity is u = J + a/2, a = F/rho.
+ *
+ * Errors: every entry point returns lbm_status (0 = success, negative =
+ * failure); no exception crosses the ABI.  Argument checks run on the host
+ * before any device work, so they can be exercised without a GPU.  The text of
+ * the last error of a context is returned by lbm_last_error (errors raised
+ * before a context exists are reported by lbm_last_error(NULL)).
+ * A context is used by one host thread at a time; calls on one context are not
+ * thread-safe.  All device work of a context is ordered on its stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque; owned by the library */
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,         /* invalid argument (NULL, sizes, parameter ranges) */
+  LBM_ERR_UNSUPPORTED = -2, /* valid but not provided (lattice, mixed precisions) */
+  LBM_ERR_OOM = -3,         /* device allocation failed */
+  LBM_ERR_DEVICE = -4,      /* a HIP call failed */
+  LBM_ERR_UNSTABLE = -5,    /* non-finite state detected (NaN / Inf) */
+  LBM_ERR_STATE = -6        /* call out of order (e.g. step before init) */
+} lbm_status;
+
+typedef enum { LBM_D3Q27 = 0 } lbm_lattice; /* D3Q27 (Sec. I, II.B); others -> UNSUPPORTED */
+
+typedef enum {
+  LBM_PERIODIC = 0,
+  LBM_WALL = 1 /* no-slip half-way bounce-back + zero normal derivative of phi */
+} lbm_bc;
+
+typedef enum {
+  LBM_FP64 = 0,    /* FP64 storage and arithmetic */
+  LBM_FP32 = 1,    /* FP32 storage and arithmetic; rho, nu, omega in FP64 */
+  LBM_FP16_OS = 2, /* phi FP32; 10 moments FP16 offset-and-scale; FP32 arithmetic */
+  LBM_BF16_OS = 3  /* phi FP32; 10 moments BF16 offset-and-scale; FP32 arithmetic */
+} lbm_precision;
+
+enum {
+  /* Advect phi with u.grad(phi) as printed in the FTCS update of Sec. II.D
+   * instead of the conservative flux form div(phi u). */
+  LBM_LITERAL_ADVECTION = 1
+};
+
+/* One box.  phi = 1 is the liquid (subscript l), phi = 0 the gas (g). */
+typedef struct {
+  int32_t nx, ny, nz;     /* >= 1; >= 2 on an axis with walls */
+  int32_t lattice;        /* lbm_lattice */
+  int32_t bc[3];          /* lbm_bc per axis x, y, z */
+  int32_t precision;      /* lbm_precision; identical for all boxes of a context */
+  int32_t flags;          /* LBM_LITERAL_ADVECTION or 0 */
+  double rho_l, rho_g;    /* phase densities, > 0 (Sec. II.C) */
+  double nu_l, nu_g;      /* kinematic viscosities, > 0; omega = 1/(3 nu + 1/2) */
+  double sigma;           /* surface tension, >= 0 (Sec. II.C: beta = 12 sigma/W, kappa = 3 sigma W/2) */
+  double mobility;        /* Allen-Cahn diffusivity D = M, >= 0, FTCS-stable if <= 0.34 */
+  double width;           /* interface width W (the paper's delta), > 0 */
+  double gravity[3];      /* body force density (rho - rho_ref) * gravity (Sec. III.A) */
+  double rho_ref;
+} lbm_params;
+
+/* Device resources.  stream: a hipStream_t on which every kernel and copy of
+ * the context is enqueued (NULL: the library creates a stream of its own).
+ * alloc/free: device allocator callbacks (NULL: hipMalloc / hipFree); alloc
+ * returns device memory of at least `bytes` bytes aligned to 256 bytes, or
+ * NULL on failure.  user is passed back unchanged. */
+typedef struct {
+  void* stream;
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} lbm_device;
+
+/* Reductions over one box, accumulated in FP64 on the device. */
+typedef struct {
+  double phase_mass;      /* sum phi */
+  double pstar_sum;       /* sum p* */
+  double momentum[3];     /* sum rho u */
+  double kinetic;         /* 1/2 sum rho |u|^2 */
+  double umax;            /* max |u| */
+  double centroid_l[3];   /* sum phi x / sum phi */
+  double velocity_l[3];   /* sum phi u / sum phi */
+  double centroid_g[3];   /* sum (1-phi) x / sum (1-phi) */
+  double velocity_g[3];   /* sum (1-phi) u / sum (1-phi) (bubble centre-of-mass velocity) */
+  double p_l, p_g;        /* mean p = rho c_s^2 p* over bulk nodes phi >= 0.98 / phi <= 0.02 */
+  double n_l, n_g;        /* number of those bulk nodes */
+  int32_t nonfinite;      /* 1 if any state value is NaN or Inf */
+} lbm_diag;
+
+/* Tile / launch configuration of the fused step (chosen by lbm_autotune). */
+typedef struct {
+  int32_t block_x, block_y; /* workgroup columns; supported pairs: (32,8) (32,16) (64,4) (64,8) */
+  int32_t z_chunk;          /* planes marched by one workgroup, >= 1 */
+  int32_t persistent;       /* 0: one workgroup per tile; n > 0: n workgroups loop over tiles */
+} lbm_tuning;
+
+/* Create a context holding n_boxes >= 1 independent boxes stepped together
+ * (one launch per step covers every box).  All parameters are validated before
+ * any device call.  The state is undefined until lbm_init_phase or
+ * lbm_set_state has been called for every box.  On success *out owns all
+ * device memory of the state (2 x 11 fields per box, ping-pong). */
+lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device* dev,
+                      lbm_ctx** out);
+
+/* Initial state of one box (Sec. II.D; P = p*_0, J = u_0, Q = 0).
+ * phi: N doubles (required); u: 3N doubles or NULL (0); pstar: N doubles or
+ * NULL (0).  N = nx*ny*nz of that box.  Blocks until the copy is done. */
+lbm_status lbm_init_phase(lbm_ctx* ctx, int32_t box, const double* phi, const double* u,
+                          const double* pstar);
+
+/* Enqueue nsteps >= 0 time steps of every box on the context stream
+ * (replayed from a captured hipGraph when graphs are enabled). Asynchronous. */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* Observables of one box (Sec. II.C): rho = rho_l phi + (1-phi) rho_g,
+ * u = J + a/2 (3N, SoA), phi, p = rho c_s^2 p*.  Any pointer may be NULL.
+ * Synchronises the stream.  Returns LBM_ERR_UNSTABLE (with outputs written)
+ * if the state holds a non-finite value. */
+lbm_status lbm_get_fields(lbm_ctx* ctx, int32_t box, double* rho, double* u, double* phi,
+                          double* p);
+
+/* FP64 reductions of one box.  Synchronises; LBM_ERR_UNSTABLE if nonfinite. */
+lbm_status lbm_diagnostics(lbm_ctx* ctx, int32_t box, lbm_diag* out);
+
+/* Raw state of one box as 11 N-double planes in the order
+ * phi, P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz (decoded to FP64).
+ * get synchronises; set replaces the state (checkpoint / restart). */
+lbm_status lbm_get_state(lbm_ctx* ctx, int32_t box, double* state);
+lbm_status lbm_set_state(lbm_ctx* ctx, int32_t box, const double* state);
+
+/* Offset-and-scale encoding of the 10 moments of one box in the 16-bit
+ * storage modes: stored = (value - offset[k]) * scale[k], k over P, Jx, Jy, Jz,
+ * Qxx, Qyy, Qzz, Qxy, Qxz, Qyz.  scale must be a positive power of two.
+ * Takes effect for the next init/set_state; ignored in FP64/FP32 modes. */
+lbm_status lbm_set_encoding(lbm_ctx* ctx, int32_t box, const double* offset,
+                            const double* scale);
+
+/* Launch configuration of the fused step. */
+lbm_status lbm_set_tuning(lbm_ctx* ctx, const lbm_tuning* t);
+lbm_status lbm_get_tuning(const lbm_ctx* ctx, lbm_tuning* t);
+
+/* Time each supported tuning for `steps` steps (after one warm-up step) and
+ * keep the fastest.  Advances the state by the steps it runs.  Writes the
+ * choice to *best if non-NULL. */
+lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps, lbm_tuning* best);
+
+/* Enable (1, default) or disable (0) hipGraph capture of lbm_step. */
+lbm_status lbm_set_graphs(lbm_ctx* ctx, int32_t enabled);
+
+/* Enqueue one separate launch of the fused step per box per step instead of
+ * one launch covering all boxes (the unbatched baseline of an ensemble). */
+lbm_status lbm_step_unbatched(lbm_ctx* ctx, int32_t nsteps);
+
+/* Wait for all work enqueued on the context stream. */
+lbm_status lbm_synchronize(lbm_ctx* ctx);
+
+/* Algorithmic HBM bytes per lattice update of the fused step in this
+ * context's precision (11 fields read + 11 written). */
+double lbm_bytes_per_update(const lbm_ctx* ctx);
+
+/* Total nodes over all boxes. */
+int64_t lbm_total_nodes(const lbm_ctx* ctx);
+
+/* Release every device resource of the context.  NULL is a no-op. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Text of the last error on ctx (or of the last failed lbm_create when ctx is
+ * NULL).  Valid until the next call on the same context. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,847 @@
+// Device code of liblbm.so for gfx950 (MI355X).
+//
+// fused_step: one time step of the thread-safe D3Q27 lattice Boltzmann
+// solver with the conservative Allen-Cahn phase field (arXiv 2501.00846,
+// Sec. II.D), as a single pull-style kernel that reads the 11 moment fields of
+// buffer s and writes those of buffer 1 - s; every thread writes only its own
+// node, so no two threads ever touch the same output (the thread-safe
+// property of Sec. II.B).
+//
+// Work decomposition.  A workgroup owns an output tile of (BX-2) x (BY-2)
+// columns of one box and marches it along z over planes [z0, z1).  Its BX x BY
+// threads map one-to-one onto the tile plus a one-column halo ring.  For every
+// node plane p the workgroup
+//   (A) stages phi of plane p+1 with a two-column halo in LDS and filters it
+//       in x-y (per-axis stencils (1,4,1) and (-1,0,1)); with the filtered
+//       planes p-1, p, p+1 held in registers each thread gets the isotropic
+//       gradient and Laplacian of Sec. II.C at its node of plane p;
+//   (B) computes at that node rho, nu, omega (FP64), mu, the forces of Sec.
+//       II.C, the acceleration a = F/rho, u = J + a/2, the regularisation
+//       tensor a2 = Q + a a/4 (Eq. hermite_neq2 with the shifted equilibrium),
+//       the 17 monomial coefficients of the post-collision populations
+//       f_post(c) = w(c) g(c) (Eqs. eqts, noneqts, guoforce, LBexp), their 27
+//       values by sum factorisation, and the phase-field flux
+//       G = phi u + (4M/W) phi (1 - phi) n;
+//   (C) exchanges f_post and G through LDS: each interior thread pulls the
+//       populations that stream into its column from the 3 x 3 neighbour
+//       columns and adds their moments to the running sums of output planes
+//       p-1, p, p+1 (registers), and likewise the divergence of G.  Output
+//       plane p-1 is then complete: Q' = Pi - cs^2 P' I - J' J', the FTCS
+//       phase update phi' = phi + M lap(phi) - div(G), and 11 stores.
+// Halo work is recomputed by the halo-ring threads; nothing but the 11 state
+// fields goes to or comes from HBM.
+//
+// Walls (no-slip, neutral wetting): half-way bounce-back f_i(x) =
+// f_post_opp(i)(x) when x - c_i is behind a wall; phi ghosts mirror the
+// interior; ghost flux G = phi (-u) + kappa_AC phi (1-phi) n with the normal
+// from the mirrored phi (reflected component).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Storage formats
+// ---------------------------------------------------------------------------
+struct bf16_t {
+  uint16_t bits;
+};
+
+struct PF64 { using TM = double;   using TP = double; using R = double; static constexpr bool kOS = false; };
+struct PF32 { using TM = float;    using TP = float;  using R = float;  static constexpr bool kOS = false; };
+struct PF16 { using TM = _Float16; using TP = float;  using R = float;  static constexpr bool kOS = true; };
+struct PBF16 { using TM = bf16_t;  using TP = float;  using R = float;  static constexpr bool kOS = true; };
+
+__device__ __forceinline__ float bf16_to_f32(bf16_t v) {
+  return __uint_as_float(static_cast<uint32_t>(v.bits) << 16);
+}
+__device__ __forceinline__ bf16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) {  // Inf / NaN: keep class, quiet NaN
+    return bf16_t{static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u))};
+  }
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return bf16_t{static_cast<uint16_t>(u >> 16)};
+}
+
+template <class R> __device__ __forceinline__ R dec(double v, float, float) { return static_cast<R>(v); }
+template <class R> __device__ __forceinline__ R dec(float v, float, float) { return static_cast<R>(v); }
+template <class R> __device__ __forceinline__ R dec(_Float16 v, float off, float inv) {
+  return static_cast<R>(static_cast<float>(v) * inv + off);
+}
+template <class R> __device__ __forceinline__ R dec(bf16_t v, float off, float inv) {
+  return static_cast<R>(bf16_to_f32(v) * inv + off);
+}
+
+template <class T> struct Enc;
+template <> struct Enc<double> {
+  template <class R> __device__ static double go(R v, float, float) { return static_cast<double>(v); }
+};
+template <> struct Enc<float> {
+  template <class R> __device__ static float go(R v, float, float) { return static_cast<float>(v); }
+};
+template <> struct Enc<_Float16> {
+  template <class R> __device__ static _Float16 go(R v, float off, float scale) {
+    return static_cast<_Float16>((static_cast<float>(v) - off) * scale);
+  }
+};
+template <> struct Enc<bf16_t> {
+  template <class R> __device__ static bf16_t go(R v, float off, float scale) {
+    return f32_to_bf16((static_cast<float>(v) - off) * scale);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Index maps
+// ---------------------------------------------------------------------------
+// Coordinate i on an axis of length n: periodic wrap, or the half-way mirror
+// of a wall (-1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2).  Columns far outside
+// (never consumed) are clamped into range.
+__device__ __forceinline__ int map_axis(int i, int n, int wall, int& crossed) {
+  if (!wall) {
+    int r = i % n;
+    crossed = 0;
+    return r < 0 ? r + n : r;
+  }
+  crossed = 0;
+  if (i < 0) { i = -1 - i; crossed = 1; }
+  else if (i >= n) { i = 2 * n - 1 - i; crossed = 1; }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ int map_axis(int i, int n, int wall) {
+  int c;
+  return map_axis(i, n, wall, c);
+}
+
+// LDS slot of the population with direction (cx, cy, cz), (cx, cy) != (0, 0).
+__host__ __device__ constexpr int fslot(int cx, int cy, int cz) {
+  return (((cy + 1) * 3 + (cx + 1)) - ((((cy + 1) * 3 + (cx + 1)) > 4) ? 1 : 0)) * 3 + (cz + 1);
+}
+
+// Moment accumulator of one output plane: P, J (3), Pi = sum f c c (6).
+template <class R> struct Acc {
+  R p, jx, jy, jz, xx, yy, zz, xy, xz, yz;
+  __device__ void zero() { p = jx = jy = jz = xx = yy = zz = xy = xz = yz = R(0); }
+};
+
+// Add the moments of 9 populations v[(cy+1)*3 + (cx+1)] sharing c_z = cz.
+template <class R, int CZ>
+__device__ __forceinline__ void accum_group(const R* v, Acc<R>& a) {
+  // along x for each c_y row: s0 = sum, s1 = sum cx, s2 = sum cx^2
+  R s0[3], s1[3], s2[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const R l = v[r * 3 + 0], c = v[r * 3 + 1], h = v[r * 3 + 2];
+    s2[r] = h + l;
+    s1[r] = h - l;
+    s0[r] = s2[r] + c;
+  }
+  const R m02 = s0[2] + s0[0];
+  const R m00 = m02 + s0[1];
+  const R m01 = s0[2] - s0[0];
+  const R m10 = s1[0] + s1[1] + s1[2];
+  const R m11 = s1[2] - s1[0];
+  const R m20 = s2[0] + s2[1] + s2[2];
+  a.p += m00;
+  a.jx += m10;
+  a.jy += m01;
+  a.xx += m20;
+  a.yy += m02;
+  a.xy += m11;
+  if (CZ != 0) {
+    a.zz += m00;
+    if (CZ > 0) { a.jz += m00; a.xz += m10; a.yz += m01; }
+    else        { a.jz -= m00; a.xz -= m10; a.yz -= m01; }
+  }
+}
+
+template <int BX, int BY, class PR>
+struct FusedShared {
+  using R = typename PR::R;
+  static constexpr int NT = BX * BY;
+  R phi[(BY + 2) * (BX + 2)];
+  R f[24 * NT];
+  R g[3 * NT];
+  R gg[3 * NT];
+};
+
+// ---------------------------------------------------------------------------
+// The fused step
+// ---------------------------------------------------------------------------
+template <int BX, int BY, class PR>
+__global__ void __launch_bounds__(BX * BY)
+fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, int n_items,
+           int parity) {
+  using TM = typename PR::TM;
+  using TP = typename PR::TP;
+  using R = typename PR::R;
+  constexpr int NT = BX * BY;
+  constexpr int PX = BX + 2;
+  constexpr int PY = BY + 2;
+  __shared__ FusedShared<BX, BY, PR> sh;
+
+  const int tid = threadIdx.x;
+  const int tx = tid % BX;
+  const int ty = tid / BX;
+
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const Item item = items[it];
+    const BoxDesc& b = boxes[item.box];
+    const int nx = b.nx, ny = b.ny, nz = b.nz;
+    const int wx = b.wall[0], wy = b.wall[1], wz = b.wall[2];
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+
+    const int x = item.x0 - 1 + tx;
+    const int y = item.y0 - 1 + ty;
+    int crx, cry;
+    const int xm = map_axis(x, nx, wx, crx);
+    const int ym = map_axis(y, ny, wy, cry);
+    const int64_t col = static_cast<int64_t>(ym) * nx + xm;
+    const bool out_col = tx >= 1 && tx <= BX - 2 && ty >= 1 && ty <= BY - 2 && x < nx && y < ny;
+    const bool ghost_col = crx || cry;
+
+    // uniform: does this tile touch a wall in x or y?
+    const bool wall_tile = (wx && (item.x0 == 0 || item.x0 + BX - 2 >= nx)) ||
+                           (wy && (item.y0 == 0 || item.y0 + BY - 2 >= ny));
+
+    const TP* __restrict__ s_phi_g = static_cast<const TP*>(b.fld[parity][0]);
+    const TM* __restrict__ s_m[10];
+    TM* __restrict__ d_m[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      s_m[k] = static_cast<const TM*>(b.fld[parity][k + 1]);
+      d_m[k] = static_cast<TM*>(b.fld[1 - parity][k + 1]);
+    }
+    TP* __restrict__ d_phi_g = static_cast<TP*>(b.fld[1 - parity][0]);
+
+    const R beta4 = static_cast<R>(b.beta4);
+    const R kappa_mu = static_cast<R>(b.kappa_mu);
+    const R kappa_ac = static_cast<R>(b.kappa_ac);
+    const R mob = static_cast<R>(b.mobility);
+    const R drho3 = static_cast<R>(b.drho * (1.0 / 3.0));
+    const bool literal = (b.flags & 1) != 0;
+
+    const int z0 = item.z0, z1 = item.z1;
+    const int p_first = (wz && z0 == 0) ? 0 : z0 - 1;
+    const int p_last = (wz && z1 == nz) ? nz - 1 : z1;
+
+    // --- stage phi of plane q into LDS and x-y filter it at the own column
+    auto stage_phi = [&](int q) {
+      const int qm = map_axis(q, nz, wz);
+      const TP* src = s_phi_g + static_cast<int64_t>(qm) * plane;
+      for (int e = tid; e < PX * PY; e += NT) {
+        const int i = e % PX, j = e / PX;
+        const int gx = map_axis(item.x0 - 2 + i, nx, wx);
+        const int gy = map_axis(item.y0 - 2 + j, ny, wy);
+        sh.phi[e] = static_cast<R>(src[static_cast<int64_t>(gy) * nx + gx]);
+      }
+    };
+    // returns (A', Bx', By', phi_c): A' = s_x s_y phi, Bx' = s_y d_x phi,
+    // By' = s_x d_y phi with s = (1,4,1), d = (-1,0,1)
+    auto filter_phi = [&](R* F) {
+      R dx[3], sx[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const R* row = &sh.phi[(ty + r) * PX + tx];
+        const R l = row[0], c = row[1], h = row[2];
+        dx[r] = h - l;
+        sx[r] = l + R(4) * c + h;
+        if (r == 1) F[3] = c;
+      }
+      F[0] = sx[0] + R(4) * sx[1] + sx[2];
+      F[1] = dx[0] + R(4) * dx[1] + dx[2];
+      F[2] = sx[2] - sx[0];
+    };
+
+    R Fm[4], F0[4], Fp[4];
+    stage_phi(p_first - 1);
+    __syncthreads();
+    filter_phi(Fm);
+    __syncthreads();
+    stage_phi(p_first);
+    __syncthreads();
+    filter_phi(F0);
+    __syncthreads();
+
+    // moments of the own column, prefetched one plane ahead
+    R nxt[10];
+    auto load_moments = [&](int q, R* m) {
+      const int qm = map_axis(q, nz, wz);
+      const int64_t idx = static_cast<int64_t>(qm) * plane + col;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] = dec<R>(s_m[k][idx], b.enc_off[k + 1], b.enc_inv[k + 1]);
+    };
+    load_moments(p_first, nxt);
+
+    Acc<R> accM, acc0, accP;
+    accM.zero();
+    acc0.zero();
+    R dM = R(0), d0 = R(0), dP = R(0);
+    R phiH = R(0), lapH = R(0), advH = R(0);  // own-node phi, lap(phi), u.grad(phi) of plane p-1
+
+    auto finalize = [&](int Z, const Acc<R>& a, R d, R phic, R lapc, R advc) {
+      const int64_t idx = static_cast<int64_t>(Z) * plane + col;
+      const R P = a.p;
+      const R q_xx = a.xx - P * R(1.0 / 3.0) - a.jx * a.jx;
+      const R q_yy = a.yy - P * R(1.0 / 3.0) - a.jy * a.jy;
+      const R q_zz = a.zz - P * R(1.0 / 3.0) - a.jz * a.jz;
+      const R q_xy = a.xy - a.jx * a.jy;
+      const R q_xz = a.xz - a.jx * a.jz;
+      const R q_yz = a.yz - a.jy * a.jz;
+      const R phin = phic + mob * lapc - advc - d * R(1.0 / 72.0);
+      d_phi_g[idx] = Enc<TP>::go(phin, 0.f, 1.f);
+      const R mv[10] = {P, a.jx, a.jy, a.jz, q_xx, q_yy, q_zz, q_xy, q_xz, q_yz};
+#pragma unroll
+      for (int k = 0; k < 10; ++k) d_m[k][idx] = Enc<TM>::go(mv[k], b.enc_off[k + 1], b.enc_scale[k + 1]);
+    };
+
+    for (int p = p_first; p <= p_last; ++p) {
+      R cur[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) cur[k] = nxt[k];
+      if (p < p_last) load_moments(p + 1, nxt);
+
+      // (A) phi plane p+1 -> LDS -> filtered registers
+      stage_phi(p + 1);
+      __syncthreads();
+      filter_phi(Fp);
+
+      // (B) node quantities at (column, p)
+      const R phi = F0[3];
+      R gx = (Fm[1] + R(4) * F0[1] + Fp[1]) * R(1.0 / 72.0);
+      R gy = (Fm[2] + R(4) * F0[2] + Fp[2]) * R(1.0 / 72.0);
+      const R gz = (Fp[0] - Fm[0]) * R(1.0 / 72.0);
+      const R lap = (Fm[0] + R(4) * F0[0] + Fp[0]) * R(1.0 / 36.0) - R(6) * phi;
+      // gradient seen from the mirrored node (ghost columns of wall axes)
+      const R gmx = crx ? -gx : gx;
+      const R gmy = cry ? -gy : gy;
+
+      const R P = cur[0];
+      const R Jx = cur[1], Jy = cur[2], Jz = cur[3];
+      const R Qxx = cur[4], Qyy = cur[5], Qzz = cur[6], Qxy = cur[7], Qxz = cur[8], Qyz = cur[9];
+
+      // density, viscosity and relaxation interpolation in FP64 (Sec. II.C)
+      const double phid = static_cast<double>(phi);
+      const double rho = b.rho_g + phid * b.drho;
+      const double inv_rho = 1.0 / rho;
+      const double nu = b.nu_g + phid * b.dnu;
+      const double om_d = 1.0 / (3.0 * nu + 0.5);
+      const double bfac = 1.0 - b.rho_ref * inv_rho;  // body acceleration factor
+      const R om1 = static_cast<R>(1.0 - om_d);
+      const R irho = static_cast<R>(inv_rho);
+      const R cvis = static_cast<R>(-3.0 * nu * om_d * b.drho * inv_rho);
+
+      // chemical potential and the force per unit mass a = F / rho
+      const R mu = beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - kappa_mu * lap;
+      const R csp = (mu - P * drho3) * irho;  // (F^s + F^p) / rho on grad(phi)
+      const R qgx = Qxx * gmx + Qxy * gmy + Qxz * gz;
+      const R qgy = Qxy * gmx + Qyy * gmy + Qyz * gz;
+      const R qgz = Qxz * gmx + Qyz * gmy + Qzz * gz;
+      const R ax = csp * gmx + cvis * qgx + static_cast<R>(b.grav[0] * bfac);
+      const R ay = csp * gmy + cvis * qgy + static_cast<R>(b.grav[1] * bfac);
+      const R az = csp * gz + cvis * qgz + static_cast<R>(b.grav[2] * bfac);
+      const R ux = Jx + R(0.5) * ax;
+      const R uy = Jy + R(0.5) * ay;
+      const R uz = Jz + R(0.5) * az;
+
+      // a2 = Q + J J - u u + (u a + a u)/2 = Q + a a / 4
+      const R Axx = Qxx + R(0.25) * ax * ax;
+      const R Ayy = Qyy + R(0.25) * ay * ay;
+      const R Azz = Qzz + R(0.25) * az * az;
+      const R Axy = Qxy + R(0.25) * ax * ay;
+      const R Axz = Qxz + R(0.25) * ax * az;
+      const R Ayz = Qyz + R(0.25) * ay * az;
+
+      // monomial coefficients of g(c) = f_post(c) / w(c), pre-scaled by 1/216
+      const R usq = ux * ux + uy * uy + uz * uz;
+      const R trA = Axx + Ayy + Azz;
+      const R ua = ux * ax + uy * ay + uz * az;
+      const R Aux = Axx * ux + Axy * uy + Axz * uz;
+      const R Auy = Axy * ux + Ayy * uy + Ayz * uz;
+      const R Auz = Axz * ux + Ayz * uy + Azz * uz;
+      constexpr R s = R(1.0 / 216.0);
+      const R G0 = s * (P - R(1.5) * (usq + om1 * trA + ua));
+      const R Gx = s * (R(3) * ux - R(4.5) * ux * (uy * uy + uz * uz) +
+                        om1 * (R(13.5) * ux * Axx - R(4.5) * ux * trA - R(9) * Aux) + R(1.5) * ax);
+      const R Gy = s * (R(3) * uy - R(4.5) * uy * (ux * ux + uz * uz) +
+                        om1 * (R(13.5) * uy * Ayy - R(4.5) * uy * trA - R(9) * Auy) + R(1.5) * ay);
+      const R Gz = s * (R(3) * uz - R(4.5) * uz * (ux * ux + uy * uy) +
+                        om1 * (R(13.5) * uz * Azz - R(4.5) * uz * trA - R(9) * Auz) + R(1.5) * az);
+      const R Gxx = (R(4.5) * s) * (ux * ux + om1 * Axx + ux * ax);
+      const R Gyy = (R(4.5) * s) * (uy * uy + om1 * Ayy + uy * ay);
+      const R Gzz = (R(4.5) * s) * (uz * uz + om1 * Azz + uz * az);
+      const R Gxy = s * (R(9) * (ux * uy + om1 * Axy) + R(4.5) * (ux * ay + uy * ax));
+      const R Gxz = s * (R(9) * (ux * uz + om1 * Axz) + R(4.5) * (ux * az + uz * ax));
+      const R Gyz = s * (R(9) * (uy * uz + om1 * Ayz) + R(4.5) * (uy * az + uz * ay));
+      constexpr R s3 = R(13.5 / 216.0);
+      const R Gxxy = s3 * (ux * ux * uy + om1 * (uy * Axx + R(2) * ux * Axy));
+      const R Gxxz = s3 * (ux * ux * uz + om1 * (uz * Axx + R(2) * ux * Axz));
+      const R Gyyx = s3 * (uy * uy * ux + om1 * (ux * Ayy + R(2) * uy * Axy));
+      const R Gyyz = s3 * (uy * uy * uz + om1 * (uz * Ayy + R(2) * uy * Ayz));
+      const R Gzzx = s3 * (uz * uz * ux + om1 * (ux * Azz + R(2) * uz * Axz));
+      const R Gzzy = s3 * (uz * uz * uy + om1 * (uy * Azz + R(2) * uz * Ayz));
+      const R Gxyz = R(27.0 / 216.0) * (ux * uy * uz + om1 * (ux * Ayz + uy * Axz + uz * Axy));
+
+      // evaluate w(c) g(c) at the 27 velocities: x, then y, then z, with the
+      // one-dimensional weights (1, 4, 1) (x 1/216 folded in above)
+      auto xb = [](R c0, R c1, R c2, R* o) { o[0] = c0 - c1 + c2; o[1] = R(4) * c0; o[2] = c0 + c1 + c2; };
+      R B00[3], B01[3], B02[3], B10[3], B11[3], B12[3], B20[3], B21[3];
+      xb(G0, Gx, Gxx, B00);
+      xb(Gy, Gxy, Gxxy, B01);
+      xb(Gyy, Gyyx, R(0), B02);
+      xb(Gz, Gxz, Gxxz, B10);
+      xb(Gyz, Gxyz, R(0), B11);
+      xb(Gyyz, R(0), R(0), B12);
+      xb(Gzz, Gzzx, R(0), B20);
+      xb(Gzzy, R(0), R(0), B21);
+      R fo[3];  // own column (cx, cy) = (0, 0), cz = -1, 0, 1
+#pragma unroll
+      for (int cyi = 0; cyi < 3; ++cyi) {
+#pragma unroll
+        for (int cxi = 0; cxi < 3; ++cxi) {
+          const int cy = cyi - 1, cx = cxi - 1;
+          R p0, p1, p2;
+          if (cy == 0) {
+            p0 = R(4) * B00[cxi];
+            p1 = R(4) * B10[cxi];
+            p2 = R(4) * B20[cxi];
+          } else {
+            p0 = B00[cxi] + B02[cxi] + (cy > 0 ? B01[cxi] : -B01[cxi]);
+            p1 = B10[cxi] + B12[cxi] + (cy > 0 ? B11[cxi] : -B11[cxi]);
+            p2 = B20[cxi] + (cy > 0 ? B21[cxi] : -B21[cxi]);
+          }
+          const R fm = p0 + p2 - p1;  // cz = -1
+          const R f0 = R(4) * p0;     // cz = 0
+          const R fp = p0 + p2 + p1;  // cz = +1
+          if (cx == 0 && cy == 0) {
+            fo[0] = fm;
+            fo[1] = f0;
+            fo[2] = fp;
+          } else {
+            sh.f[fslot(cx, cy, -1) * NT + tid] = fm;
+            sh.f[fslot(cx, cy, 0) * NT + tid] = f0;
+            sh.f[fslot(cx, cy, 1) * NT + tid] = fp;
+          }
+        }
+      }
+
+      // phase-field flux G at this node (ghost rules on mirrored columns)
+      {
+        const R gm = sqrt(gx * gx + gy * gy + gz * gz) + R(1e-12);
+        const R ig = R(1) / gm;
+        const R sharp = kappa_ac * phi * (R(1) - phi) * ig;
+        const R us = (crx ^ cry) ? R(-1) : R(1);
+        const R pu = literal ? R(0) : phi * us;
+        const R Gfx = pu * ux + sharp * gx;
+        const R Gfy = pu * uy + sharp * gy;
+        const R Gfz = pu * uz + sharp * gz;
+        sh.g[0 * NT + tid] = Gfx;
+        sh.g[1 * NT + tid] = Gfy;
+        sh.g[2 * NT + tid] = Gfz;
+        if (wz && (p == 0 || p == nz - 1)) {
+          // ghost plane beyond the z wall: velocity reversed, n_z reversed
+          sh.gg[0 * NT + tid] = -pu * ux + sharp * gx;
+          sh.gg[1 * NT + tid] = -pu * uy + sharp * gy;
+          sh.gg[2 * NT + tid] = -pu * uz - sharp * gz;
+        }
+      }
+      const R adv_own = literal ? (ux * gmx + uy * gmy + uz * gz) : R(0);
+      (void)ghost_col;
+      __syncthreads();
+
+      // (C) pull, accumulate, finalise output plane p-1
+      if (out_col) {
+        accP.zero();
+        const bool zb_lo = wz && p == 0;
+        const bool zb_hi = wz && p == nz - 1;
+        // regular pulls from the 3 x 3 neighbour columns
+#pragma unroll
+        for (int czi = 0; czi < 3; ++czi) {
+          R v[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            const int cx = k % 3 - 1, cy = k / 3 - 1;
+            if (k == 4) v[k] = fo[czi];
+            else v[k] = sh.f[fslot(cx, cy, czi - 1) * NT + tid - cy * BX - cx];
+          }
+          if (wall_tile) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+              const int cx = k % 3 - 1, cy = k / 3 - 1;
+              const bool outside = (wx && (x - cx < 0 || x - cx >= nx)) ||
+                                   (wy && (y - cy < 0 || y - cy >= ny));
+              if (outside) v[k] = R(0);
+            }
+          }
+          if (czi == 0) accum_group<R, -1>(v, accM);
+          else if (czi == 1) accum_group<R, 0>(v, acc0);
+          else accum_group<R, 1>(v, accP);
+        }
+        // half-way bounce-back into this node (plane p)
+        if (wall_tile || zb_lo || zb_hi) {
+#pragma unroll
+          for (int czi = 0; czi < 3; ++czi) {
+            const int cz = czi - 1;
+            const bool zb = (zb_lo && cz == 1) || (zb_hi && cz == -1);
+            R v[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+              const int cx = k % 3 - 1, cy = k / 3 - 1;
+              const bool outside = (wx && (x - cx < 0 || x - cx >= nx)) ||
+                                   (wy && (y - cy < 0 || y - cy >= ny));
+              R own;
+              if (k == 4) own = fo[2 - czi];
+              else own = sh.f[fslot(-cx, -cy, -cz) * NT + tid];
+              v[k] = (outside || zb) ? own : R(0);
+            }
+            if (czi == 0) accum_group<R, -1>(v, acc0);
+            else if (czi == 1) accum_group<R, 0>(v, acc0);
+            else accum_group<R, 1>(v, acc0);
+          }
+        }
+        // divergence of the phase-field flux (forward neighbours x + c)
+        {
+          auto G = [&](int comp, int cx, int cy) { return sh.g[comp * NT + tid + cy * BX + cx]; };
+          R hx = R(0), hy = R(0), hz = R(0);
+#pragma unroll
+          for (int cy = -1; cy <= 1; ++cy) {
+            const R wyv = cy == 0 ? R(4) : R(1);
+            hx += wyv * (G(0, 1, cy) - G(0, -1, cy));
+          }
+#pragma unroll
+          for (int cx = -1; cx <= 1; ++cx) {
+            const R wxv = cx == 0 ? R(4) : R(1);
+            hy += wxv * (G(1, cx, 1) - G(1, cx, -1));
+          }
+#pragma unroll
+          for (int cy = -1; cy <= 1; ++cy) {
+#pragma unroll
+            for (int cx = -1; cx <= 1; ++cx) {
+              const R w = (cx == 0 ? R(4) : R(1)) * (cy == 0 ? R(4) : R(1));
+              hz += w * G(2, cx, cy);
+            }
+          }
+          const R hxy = hx + hy;
+          dM += hxy + hz;
+          d0 += R(4) * hxy;
+          dP = hxy - hz;
+          if (zb_lo || zb_hi) {
+            auto GG = [&](int comp, int cx, int cy) { return sh.gg[comp * NT + tid + cy * BX + cx]; };
+            R gx2 = R(0), gy2 = R(0), gz2 = R(0);
+#pragma unroll
+            for (int cy = -1; cy <= 1; ++cy) {
+              const R wyv = cy == 0 ? R(4) : R(1);
+              gx2 += wyv * (GG(0, 1, cy) - GG(0, -1, cy));
+            }
+#pragma unroll
+            for (int cx = -1; cx <= 1; ++cx) {
+              const R wxv = cx == 0 ? R(4) : R(1);
+              gy2 += wxv * (GG(1, cx, 1) - GG(1, cx, -1));
+            }
+#pragma unroll
+            for (int cy = -1; cy <= 1; ++cy) {
+#pragma unroll
+              for (int cx = -1; cx <= 1; ++cx) {
+                const R w = (cx == 0 ? R(4) : R(1)) * (cy == 0 ? R(4) : R(1));
+                gz2 += w * GG(2, cx, cy);
+              }
+            }
+            // plane -1 feeds output 0 with (Hxy - Hz); plane nz feeds nz-1 with (Hxy + Hz)
+            if (zb_lo) d0 += (gx2 + gy2) - gz2;
+            if (zb_hi) d0 += (gx2 + gy2) + gz2;
+          }
+        }
+        if (p - 1 >= z0 && p - 1 < z1) finalize(p - 1, accM, dM, phiH, lapH, advH);
+        accM = acc0;
+        acc0 = accP;
+        dM = d0;
+        d0 = dP;
+        phiH = phi;
+        lapH = lap;
+        advH = adv_own;
+      }
+      // rotate the filtered phi planes
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Fm[k] = F0[k];
+        F0[k] = Fp[k];
+      }
+    }
+    // top wall: the last node plane is the last output plane
+    if (out_col && wz && z1 == nz) finalize(nz - 1, accM, dM, phiH, lapH, advH);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Non-hot kernels: encode / decode / observables / diagnostics
+// ---------------------------------------------------------------------------
+template <class PR>
+__global__ void encode_kernel(BoxDesc b, int parity, int field, const double* __restrict__ src, int64_t n) {
+  using TM = typename PR::TM;
+  using TP = typename PR::TP;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (field == 0) static_cast<TP*>(b.fld[parity][0])[i] = Enc<TP>::go(src[i], 0.f, 1.f);
+    else static_cast<TM*>(b.fld[parity][field])[i] = Enc<TM>::go(src[i], b.enc_off[field], b.enc_scale[field]);
+  }
+}
+
+template <class PR>
+__global__ void decode_kernel(BoxDesc b, int parity, int field, double* __restrict__ dst, int64_t n) {
+  using TM = typename PR::TM;
+  using TP = typename PR::TP;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (field == 0) dst[i] = dec<double>(static_cast<const TP*>(b.fld[parity][0])[i], 0.f, 1.f);
+    else dst[i] = dec<double>(static_cast<const TM*>(b.fld[parity][field])[i], b.enc_off[field], b.enc_inv[field]);
+  }
+}
+
+// Node quantities needed by the observables and diagnostics, in FP64 from
+// the decoded state: rho, u = J + a/2, p = rho cs^2 p*.
+template <class PR>
+__device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, double& rho, double u[3],
+                         double& phi, double& p, double& pstar, bool& finite) {
+  using TM = typename PR::TM;
+  using TP = typename PR::TP;
+  const int nx = b.nx, ny = b.ny, nz = b.nz;
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const TP* fphi = static_cast<const TP*>(b.fld[parity][0]);
+  double m[10];
+  const int64_t idx = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
+  finite = true;
+  for (int k = 0; k < 10; ++k) {
+    m[k] = dec<double>(static_cast<const TM*>(b.fld[parity][k + 1])[idx], b.enc_off[k + 1], b.enc_inv[k + 1]);
+    finite = finite && isfinite(m[k]);
+  }
+  phi = dec<double>(fphi[idx], 0.f, 1.f);
+  finite = finite && isfinite(phi);
+  double g[3] = {0, 0, 0}, lap = 0;
+  for (int cz = -1; cz <= 1; ++cz)
+    for (int cy = -1; cy <= 1; ++cy)
+      for (int cx = -1; cx <= 1; ++cx) {
+        const int xx = map_axis(x + cx, nx, b.wall[0]);
+        const int yy = map_axis(y + cy, ny, b.wall[1]);
+        const int zz = map_axis(z + cz, nz, b.wall[2]);
+        const double v = dec<double>(fphi[static_cast<int64_t>(zz) * plane + static_cast<int64_t>(yy) * nx + xx], 0.f, 1.f);
+        const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
+        g[0] += 3.0 * w * cx * v;
+        g[1] += 3.0 * w * cy * v;
+        g[2] += 3.0 * w * cz * v;
+        lap += 6.0 * w * (v - phi);
+      }
+  rho = b.rho_g + phi * b.drho;
+  const double nu = b.nu_g + phi * b.dnu;
+  const double om = 1.0 / (3.0 * nu + 0.5);
+  const double mu = b.beta4 * phi * (phi - 1.0) * (phi - 0.5) - b.kappa_mu * lap;
+  const double P = m[0];
+  const double Q[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+  for (int a = 0; a < 3; ++a) {
+    double qg = 0;
+    for (int c = 0; c < 3; ++c) qg += Q[a][c] * g[c] * b.drho;
+    const double F = mu * g[a] - P * (1.0 / 3.0) * b.drho * g[a] - 3.0 * nu * om * qg +
+                     (rho - b.rho_ref) * b.grav[a];
+    u[a] = m[1 + a] + 0.5 * F / rho;
+  }
+  pstar = P;
+  p = rho * (1.0 / 3.0) * P;
+}
+
+template <class PR>
+__global__ void observable_kernel(BoxDesc b, int parity, int which, double* __restrict__ dst) {
+  const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int x = static_cast<int>(i % b.nx);
+    const int y = static_cast<int>((i / b.nx) % b.ny);
+    const int z = static_cast<int>(i / (static_cast<int64_t>(b.nx) * b.ny));
+    double rho, u[3], phi, p, ps;
+    bool fin;
+    node_obs<PR>(b, parity, x, y, z, rho, u, phi, p, ps, fin);
+    double v = 0;
+    switch (which) {
+      case 0: v = rho; break;
+      case 1: v = u[0]; break;
+      case 2: v = u[1]; break;
+      case 3: v = u[2]; break;
+      case 4: v = phi; break;
+      default: v = p; break;
+    }
+    dst[i] = v;
+  }
+}
+
+// Diagnostics value layout (kDiagValues doubles):
+//  0 sum phi | 1 sum p* | 2-4 sum rho u | 5 sum rho|u|^2/2 | 6 max|u|
+//  7-9 sum phi x | 10-12 sum phi u | 13 sum (1-phi) | 14-16 sum (1-phi) x
+//  17-19 sum (1-phi) u | 20 sum p (phi>=0.98) | 21 count | 22 sum p (phi<=0.02)
+//  23 count | 24 nonfinite flag | 25-27 unused
+constexpr int kDiagThreads = 256;
+
+__device__ inline double combine(int k, double a, double b) {
+  if (k == 6 || k == 24) return a > b ? a : b;
+  return a + b;
+}
+
+template <class PR>
+__global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(BoxDesc b, int parity, double* __restrict__ partials) {
+  __shared__ double red[kDiagThreads];
+  double acc[kDiagValues];
+  for (int k = 0; k < kDiagValues; ++k) acc[k] = 0.0;
+  const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int x = static_cast<int>(i % b.nx);
+    const int y = static_cast<int>((i / b.nx) % b.ny);
+    const int z = static_cast<int>(i / (static_cast<int64_t>(b.nx) * b.ny));
+    double rho, u[3], phi, p, ps;
+    bool fin;
+    node_obs<PR>(b, parity, x, y, z, rho, u, phi, p, ps, fin);
+    const double sp = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double pos[3] = {double(x), double(y), double(z)};
+    acc[0] += phi;
+    acc[1] += ps;
+    for (int a = 0; a < 3; ++a) acc[2 + a] += rho * u[a];
+    acc[5] += 0.5 * rho * sp;
+    acc[6] = fmax(acc[6], sqrt(sp));
+    for (int a = 0; a < 3; ++a) {
+      acc[7 + a] += phi * pos[a];
+      acc[10 + a] += phi * u[a];
+      acc[14 + a] += (1.0 - phi) * pos[a];
+      acc[17 + a] += (1.0 - phi) * u[a];
+    }
+    acc[13] += 1.0 - phi;
+    if (phi >= 0.98) { acc[20] += p; acc[21] += 1.0; }
+    if (phi <= 0.02) { acc[22] += p; acc[23] += 1.0; }
+    if (!fin) acc[24] = 1.0;
+  }
+  // block reduction, fixed order
+  for (int k = 0; k < kDiagValues; ++k) {
+    red[threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] = combine(k, red[threadIdx.x], red[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x * kDiagValues + k] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kDiagThreads) diag_final_kernel(const double* __restrict__ partials, int nblocks,
+                                                                  double* __restrict__ out) {
+  __shared__ double red[kDiagThreads];
+  for (int k = 0; k < kDiagValues; ++k) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += kDiagThreads) a = combine(k, a, partials[i * kDiagValues + k]);
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] = combine(k, red[threadIdx.x], red[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0];
+    __syncthreads();
+  }
+}
+
+template <class F>
+hipError_t dispatch(int precision, F&& f) {
+  switch (precision) {
+    case kF64: return f(PF64{});
+    case kF32: return f(PF32{});
+    case kF16: return f(PF16{});
+    case kBF16: return f(PBF16{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return static_cast<int>(g);
+}
+
+template <int BX, int BY>
+hipError_t launch_fused_t(int precision, const BoxDesc* d_boxes, const Item* d_items, int n_items,
+                          int grid, int parity, hipStream_t stream) {
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((fused_step<BX, BY, PR>), dim3(grid), dim3(BX * BY), 0, stream, d_boxes, d_items,
+                       n_items, parity);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace
+
+bool fused_config_supported(int bx, int by) {
+  return (bx == 32 && by == 8) || (bx == 32 && by == 16) || (bx == 64 && by == 4) || (bx == 64 && by == 8);
+}
+
+hipError_t launch_fused(int precision, int bx, int by, const BoxDesc* d_boxes, const Item* d_items,
+                        int n_items, int grid, int parity, hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  if (grid <= 0 || grid > n_items) grid = n_items;
+  if (bx == 32 && by == 8) return launch_fused_t<32, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 32 && by == 16) return launch_fused_t<32, 16>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 64 && by == 4) return launch_fused_t<64, 4>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 64 && by == 8) return launch_fused_t<64, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_encode(int precision, const BoxDesc& box, int parity, int field, const double* d_src,
+                         int64_t n, hipStream_t stream) {
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((encode_kernel<PR>), dim3(grid_for(n, 256)), dim3(256), 0, stream, box, parity, field,
+                       d_src, n);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_decode(int precision, const BoxDesc& box, int parity, int field, double* d_dst, int64_t n,
+                         hipStream_t stream) {
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((decode_kernel<PR>), dim3(grid_for(n, 256)), dim3(256), 0, stream, box, parity, field,
+                       d_dst, n);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_observable(int precision, const BoxDesc& box, int parity, int which, double* d_dst,
+                             hipStream_t stream) {
+  const int64_t n = static_cast<int64_t>(box.nx) * box.ny * box.nz;
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((observable_kernel<PR>), dim3(grid_for(n, 256)), dim3(256), 0, stream, box, parity,
+                       which, d_dst);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_diagnostics(int precision, const BoxDesc& box, int parity, double* d_partials, double* d_out,
+                              hipStream_t stream) {
+  const int64_t n = static_cast<int64_t>(box.nx) * box.ny * box.nz;
+  int nb = grid_for(n, kDiagThreads);
+  if (nb > kDiagBlocks) nb = kDiagBlocks;
+  hipError_t e = dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((diag_partial_kernel<PR>), dim3(nb), dim3(kDiagThreads), 0, stream, box, parity,
+                       d_partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagThreads), 0, stream, d_partials, nb, d_out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

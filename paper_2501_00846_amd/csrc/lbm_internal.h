@@ -1,0 +1,68 @@
+// Internal interface between the host runtime (runtime.cpp) and the device
+// code (kernels.hip) of liblbm.so.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm {
+
+constexpr int kFields = 11;  // phi, P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
+
+// Per-box constants and state pointers, resident in device memory; read with
+// uniform (scalar) loads by every workgroup working on the box.
+struct BoxDesc {
+  void* fld[2][kFields];  // ping-pong buffers: fld[parity][field]
+  int32_t nx, ny, nz;
+  int32_t wall[3];        // 1 if the axis has walls
+  int32_t flags;          // LBM_LITERAL_ADVECTION
+  int32_t pad0;
+  double rho_g, drho;     // rho = rho_g + phi * drho
+  double nu_g, dnu;       // nu = nu_g + phi * dnu
+  double beta4;           // 4 beta = 48 sigma / W
+  double kappa_mu;        // 3 sigma W / 2
+  double mobility;        // M
+  double kappa_ac;        // 4 M / W
+  double grav[3];
+  double rho_ref;
+  float enc_off[kFields];   // stored = (v - off) * scale in 16-bit modes
+  float enc_scale[kFields];
+  float enc_inv[kFields];   // 1 / scale (exact: powers of two)
+  int32_t pad1;
+};
+
+// One unit of work of the fused step: an output tile (x0, y0) of one box,
+// marched over output planes [z0, z1).
+struct Item {
+  int32_t box, x0, y0, z0, z1, pad[3];
+};
+
+enum Precision { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
+
+// Fused step over n_items tiles; reads buffer `parity`, writes 1 - parity.
+// grid workgroups loop over the items with stride grid.
+hipError_t launch_fused(int precision, int block_x, int block_y, const BoxDesc* d_boxes,
+                        const Item* d_items, int n_items, int grid, int parity,
+                        hipStream_t stream);
+bool fused_config_supported(int block_x, int block_y);
+
+// Encode N doubles into field `field` (storage of `precision`).
+hipError_t launch_encode(int precision, const BoxDesc& box, int parity, int field,
+                         const double* d_src, int64_t n, hipStream_t stream);
+// Decode field `field` into N doubles.
+hipError_t launch_decode(int precision, const BoxDesc& box, int parity, int field,
+                         double* d_dst, int64_t n, hipStream_t stream);
+// Observable `which` (0 rho, 1 ux, 2 uy, 3 uz, 4 phi, 5 p) into N doubles.
+hipError_t launch_observable(int precision, const BoxDesc& box, int parity, int which,
+                             double* d_dst, hipStream_t stream);
+
+constexpr int kDiagValues = 28;
+constexpr int kDiagBlocks = 1024;
+// FP64 reductions of one box: partials (kDiagBlocks * kDiagValues doubles),
+// then the final kDiagValues doubles into d_out (deterministic order).
+hipError_t launch_diagnostics(int precision, const BoxDesc& box, int parity, double* d_partials,
+                              double* d_out, hipStream_t stream);
+
+}  // namespace lbm

@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/lbm.h, and rejects bad arguments with the documented
+status codes before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2501_00846_amd import lbm
+from paper_2501_00846_amd.workloads import Problem, PERIODIC, WALL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load_library()
+    names = declared_functions()
+    assert "lbm_create" in names and "lbm_step" in names and len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in lbm._SIGS, "binding lacks " + name
+
+
+def _params(**kw):
+    prob = Problem(8, 8, 8)
+    p = lbm.make_params(prob)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _create(params, n=None):
+    lib = lbm.load_library()
+    out = ctypes.c_void_p()
+    arr = (lbm.lbm_params * len(params))(*params)
+    st = lib.lbm_create(arr, len(params) if n is None else n, None, ctypes.byref(out))
+    return st, out, lbm.lbm_last_error(None)
+
+
+@pytest.mark.parametrize("kw,code,frag", [
+    (dict(nx=0), -1, "dims"),
+    (dict(nz=-3), -1, "dims"),
+    (dict(lattice=1), -2, "lattice"),
+    (dict(width=0.0), -1, "width"),
+    (dict(width=float("nan")), -1, "width"),
+    (dict(nu_l=0.0), -1, "viscosit"),
+    (dict(nu_g=-1.0), -1, "viscosit"),
+    (dict(rho_g=0.0), -1, "densit"),
+    (dict(sigma=-1.0), -1, "sigma"),
+    (dict(mobility=-0.1), -1, "mobility"),
+    (dict(precision=7), -1, "precision"),
+    (dict(flags=8), -1, "flags"),
+])
+def test_create_rejects_bad_parameters(kw, code, frag):
+    st, out, msg = _create([_params(**kw)])
+    assert st == code
+    assert out.value is None
+    assert frag in msg
+
+
+def test_create_rejects_wall_axis_of_one_node():
+    p = _params(nz=1)
+    p.bc[2] = WALL
+    st, _, msg = _create([p])
+    assert st == -1 and "wall" in msg
+
+
+def test_create_rejects_mixed_precisions():
+    st, _, msg = _create([_params(precision=0), _params(precision=1)])
+    assert st == -2 and "precision" in msg
+
+
+def test_create_rejects_null_and_counts():
+    lib = lbm.load_library()
+    out = ctypes.c_void_p()
+    assert lib.lbm_create(None, 1, None, ctypes.byref(out)) == -1
+    st, _, _ = _create([_params()], n=0)
+    assert st == -1
+    arr = (lbm.lbm_params * 1)(_params())
+    assert lib.lbm_create(arr, 1, None, None) == -1
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = lbm.load_library()
+    assert lib.lbm_step(None, 1) == -1
+    assert lib.lbm_synchronize(None) == -1
+    assert lib.lbm_get_fields(None, 0, None, None, None, None) == -1
+    assert lib.lbm_bytes_per_update(None) == 0.0
+    assert lib.lbm_total_nodes(None) == 0
+    lib.lbm_destroy(None)
+
+
+def test_python_binding_raises_lbm_error():
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create([_params(nx=0)])
+    assert ei.value.status == -1
