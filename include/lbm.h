@@ -126,7 +126,7 @@ typedef struct {
 
 /* Tile / launch configuration of the fused step (chosen by lbm_autotune). */
 typedef struct {
-  int32_t block_x, block_y; /* workgroup columns; supported pairs: (32,8) (32,16) (64,4) (64,8) */
+  int32_t block_x, block_y; /* workgroup columns; supported pairs: (32,8) (34,8) (34,15), and (66,8) except in FP64 */
   int32_t z_chunk;          /* planes marched by one workgroup, >= 1 */
   int32_t persistent;       /* 0: one workgroup per tile; n > 0: n workgroups loop over tiles */
 } lbm_tuning;
@@ -164,6 +164,13 @@ lbm_status lbm_diagnostics(lbm_ctx* ctx, int32_t box, lbm_diag* out);
  * get synchronises; set replaces the state (checkpoint / restart). */
 lbm_status lbm_get_state(lbm_ctx* ctx, int32_t box, double* state);
 lbm_status lbm_set_state(lbm_ctx* ctx, int32_t box, const double* state);
+
+/* Raw state (decoded to FP64) at n chosen nodes of one box: node[j] is a
+ * flat index x + nx*(y + ny*z) in [0, N); out holds 11 planes of n doubles in
+ * the field order of lbm_get_state (out[k*n + j]).  For spot checks of large
+ * boxes without copying the whole state.  Synchronises. */
+lbm_status lbm_get_state_points(lbm_ctx* ctx, int32_t box, int64_t n, const int64_t* node,
+                                double* out);
 
 /* Offset-and-scale encoding of the 10 moments of one box in the 16-bit
  * storage modes: stored = (value - offset[k]) * scale[k], k over P, Jx, Jy, Jz,

@@ -47,25 +47,27 @@ namespace {
 // ---------------------------------------------------------------------------
 // Storage formats
 // ---------------------------------------------------------------------------
-struct bf16_t {
-  uint16_t bits;
-};
+// bfloat16 storage: the upper 16 bits of an IEEE binary32
+using bf16_t = uint16_t;
 
-struct PF64 { using TM = double;   using TP = double; using R = double; static constexpr bool kOS = false; };
-struct PF32 { using TM = float;    using TP = float;  using R = float;  static constexpr bool kOS = false; };
-struct PF16 { using TM = _Float16; using TP = float;  using R = float;  static constexpr bool kOS = true; };
-struct PBF16 { using TM = bf16_t;  using TP = float;  using R = float;  static constexpr bool kOS = true; };
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+struct PF64 { using TM = double;   using TP = double; using R = double; };
+struct PF32 { using TM = float;    using TP = float;  using R = float; };
+struct PF16 { using TM = _Float16; using TP = float;  using R = float; };
+struct PBF16 { using TM = bf16_t;  using TP = float;  using R = float; };
 
 __device__ __forceinline__ float bf16_to_f32(bf16_t v) {
-  return __uint_as_float(static_cast<uint32_t>(v.bits) << 16);
+  return __uint_as_float(static_cast<uint32_t>(v) << 16);
 }
 __device__ __forceinline__ bf16_t f32_to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
   if ((u & 0x7f800000u) == 0x7f800000u) {  // Inf / NaN: keep class, quiet NaN
-    return bf16_t{static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u))};
+    return static_cast<bf16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
   }
   u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return bf16_t{static_cast<uint16_t>(u >> 16)};
+  return static_cast<bf16_t>(u >> 16);
 }
 
 template <class R> __device__ __forceinline__ R dec(double v, float, float) { return static_cast<R>(v); }
@@ -116,6 +118,12 @@ __device__ __forceinline__ int map_axis(int i, int n, int wall, int& crossed) {
 __device__ __forceinline__ int map_axis(int i, int n, int wall) {
   int c;
   return map_axis(i, n, wall, c);
+}
+
+// Plane index map for a uniform q in [-2, n+1]: fast path inside the domain.
+__device__ __forceinline__ int map_plane(int q, int n, int wall) {
+  if (q >= 0 && q < n) return q;
+  return map_axis(q, n, wall);
 }
 
 // LDS slot of the population with direction (cx, cy, cz), (cx, cy) != (0, 0).
@@ -203,21 +211,23 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     const int ym = map_axis(y, ny, wy, cry);
     const int64_t col = static_cast<int64_t>(ym) * nx + xm;
     const bool out_col = tx >= 1 && tx <= BX - 2 && ty >= 1 && ty <= BY - 2 && x < nx && y < ny;
-    const bool ghost_col = crx || cry;
+    // per-lane flags kept in one VGPR; decoded where used inside the z loop
+    // (bit 0/1: ghost column mirrored in x/y; bits 2-5: output node next to
+    // the low-x / high-x / low-y / high-y wall)
+    const uint32_t lflags0 = (crx ? 1u : 0u) | (cry ? 2u : 0u) |
+                             ((wx && x == 0) ? 4u : 0u) | ((wx && x == nx - 1) ? 8u : 0u) |
+                             ((wy && y == 0) ? 16u : 0u) | ((wy && y == ny - 1) ? 32u : 0u);
 
     // uniform: does this tile touch a wall in x or y?
     const bool wall_tile = (wx && (item.x0 == 0 || item.x0 + BX - 2 >= nx)) ||
                            (wy && (item.y0 == 0 || item.y0 + BY - 2 >= ny));
 
-    const TP* __restrict__ s_phi_g = static_cast<const TP*>(b.fld[parity][0]);
-    const TM* __restrict__ s_m[10];
-    TM* __restrict__ d_m[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) {
-      s_m[k] = static_cast<const TM*>(b.fld[parity][k + 1]);
-      d_m[k] = static_cast<TM*>(b.fld[1 - parity][k + 1]);
-    }
-    TP* __restrict__ d_phi_g = static_cast<TP*>(b.fld[1 - parity][0]);
+    // state views: phi [z][y][x]; moments [z][k][y][x] (plane-interleaved)
+    const gptr<const TP> s_phi_g = (gptr<const TP>)(b.phi[parity]);
+    const gptr<const TM> s_mom = (gptr<const TM>)(b.mom[parity]);
+    const gptr<TP> d_phi_g = (gptr<TP>)(b.phi[1 - parity]);
+    const gptr<TM> d_mom = (gptr<TM>)(b.mom[1 - parity]);
+    const uint32_t ucol = static_cast<uint32_t>(col);
 
     const R beta4 = static_cast<R>(b.beta4);
     const R kappa_mu = static_cast<R>(b.kappa_mu);
@@ -230,15 +240,21 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     const int p_first = (wz && z0 == 0) ? 0 : z0 - 1;
     const int p_last = (wz && z1 == nz) ? nz - 1 : z1;
 
-    // --- stage phi of plane q into LDS and x-y filter it at the own column
+    // --- stage phi of plane q into LDS (halo columns resolved once per tile)
+    constexpr int NPH = (PX * PY + NT - 1) / NT;
+    uint32_t phcol[NPH];
+#pragma unroll
+    for (int j = 0; j < NPH; ++j) {
+      const int e = tid + j * NT;
+      const int i = e % PX, jj = e / PX;
+      phcol[j] = static_cast<uint32_t>(map_axis(item.y0 - 2 + jj, ny, wy) * nx + map_axis(item.x0 - 2 + i, nx, wx));
+    }
     auto stage_phi = [&](int q) {
-      const int qm = map_axis(q, nz, wz);
-      const TP* src = s_phi_g + static_cast<int64_t>(qm) * plane;
-      for (int e = tid; e < PX * PY; e += NT) {
-        const int i = e % PX, j = e / PX;
-        const int gx = map_axis(item.x0 - 2 + i, nx, wx);
-        const int gy = map_axis(item.y0 - 2 + j, ny, wy);
-        sh.phi[e] = static_cast<R>(src[static_cast<int64_t>(gy) * nx + gx]);
+      const gptr<const TP> src = s_phi_g + static_cast<int64_t>(map_plane(q, nz, wz)) * plane;
+#pragma unroll
+      for (int j = 0; j < NPH; ++j) {
+        const int e = tid + j * NT;
+        if (j < NPH - 1 || e < PX * PY) sh.phi[e] = static_cast<R>(src[phcol[j]]);
       }
     };
     // returns (A', Bx', By', phi_c): A' = s_x s_y phi, Bx' = s_y d_x phi,
@@ -270,11 +286,15 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 
     // moments of the own column, prefetched one plane ahead
     R nxt[10];
+    const uint32_t uplane = static_cast<uint32_t>(plane);
     auto load_moments = [&](int q, R* m) {
-      const int qm = map_axis(q, nz, wz);
-      const int64_t idx = static_cast<int64_t>(qm) * plane + col;
+      const gptr<const TM> base = s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * 10 * plane;
+      uint32_t off = ucol;
 #pragma unroll
-      for (int k = 0; k < 10; ++k) m[k] = dec<R>(s_m[k][idx], b.enc_off[k + 1], b.enc_inv[k + 1]);
+      for (int k = 0; k < 10; ++k) {
+        m[k] = dec<R>(base[off], b.enc_off[k], b.enc_inv[k]);
+        off += uplane;
+      }
     };
     load_moments(p_first, nxt);
 
@@ -285,7 +305,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     R phiH = R(0), lapH = R(0), advH = R(0);  // own-node phi, lap(phi), u.grad(phi) of plane p-1
 
     auto finalize = [&](int Z, const Acc<R>& a, R d, R phic, R lapc, R advc) {
-      const int64_t idx = static_cast<int64_t>(Z) * plane + col;
+      const gptr<TM> base = d_mom + static_cast<int64_t>(Z) * 10 * plane;
       const R P = a.p;
       const R q_xx = a.xx - P * R(1.0 / 3.0) - a.jx * a.jx;
       const R q_yy = a.yy - P * R(1.0 / 3.0) - a.jy * a.jy;
@@ -294,10 +314,14 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R q_xz = a.xz - a.jx * a.jz;
       const R q_yz = a.yz - a.jy * a.jz;
       const R phin = phic + mob * lapc - advc - d * R(1.0 / 72.0);
-      d_phi_g[idx] = Enc<TP>::go(phin, 0.f, 1.f);
+      d_phi_g[static_cast<int64_t>(Z) * plane + ucol] = Enc<TP>::go(phin, 0.f, 1.f);
       const R mv[10] = {P, a.jx, a.jy, a.jz, q_xx, q_yy, q_zz, q_xy, q_xz, q_yz};
+      uint32_t off = ucol;
 #pragma unroll
-      for (int k = 0; k < 10; ++k) d_m[k][idx] = Enc<TM>::go(mv[k], b.enc_off[k + 1], b.enc_scale[k + 1]);
+      for (int k = 0; k < 10; ++k) {
+        base[off] = Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]);
+        off += uplane;
+      }
     };
 
     for (int p = p_first; p <= p_last; ++p) {
@@ -317,9 +341,12 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       R gy = (Fm[2] + R(4) * F0[2] + Fp[2]) * R(1.0 / 72.0);
       const R gz = (Fp[0] - Fm[0]) * R(1.0 / 72.0);
       const R lap = (Fm[0] + R(4) * F0[0] + Fp[0]) * R(1.0 / 36.0) - R(6) * phi;
+      uint32_t lf = lflags0;
+      asm volatile("" : "+v"(lf));  // keep lane predicates in a VGPR, not hoisted masks
+      const bool gcx = (lf & 1u) != 0, gcy = (lf & 2u) != 0;
       // gradient seen from the mirrored node (ghost columns of wall axes)
-      const R gmx = crx ? -gx : gx;
-      const R gmy = cry ? -gy : gy;
+      const R gmx = gcx ? -gx : gx;
+      const R gmy = gcy ? -gy : gy;
 
       const R P = cur[0];
       const R Jx = cur[1], Jy = cur[2], Jz = cur[3];
@@ -435,7 +462,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         const R gm = sqrt(gx * gx + gy * gy + gz * gz) + R(1e-12);
         const R ig = R(1) / gm;
         const R sharp = kappa_ac * phi * (R(1) - phi) * ig;
-        const R us = (crx ^ cry) ? R(-1) : R(1);
+        const R us = (gcx != gcy) ? R(-1) : R(1);
         const R pu = literal ? R(0) : phi * us;
         const R Gfx = pu * ux + sharp * gx;
         const R Gfy = pu * uy + sharp * gy;
@@ -451,7 +478,12 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         }
       }
       const R adv_own = literal ? (ux * gmx + uy * gmy + uz * gz) : R(0);
-      (void)ghost_col;
+      // ghost columns contribute no regular pulls: the populations that would
+      // stream out of them are replaced by bounce-back at the wall node
+      if (wall_tile && (gcx || gcy)) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) sh.f[k * NT + tid] = R(0);
+      }
       __syncthreads();
 
       // (C) pull, accumulate, finalise output plane p-1
@@ -469,21 +501,16 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
             if (k == 4) v[k] = fo[czi];
             else v[k] = sh.f[fslot(cx, cy, czi - 1) * NT + tid - cy * BX - cx];
           }
-          if (wall_tile) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-              const int cx = k % 3 - 1, cy = k / 3 - 1;
-              const bool outside = (wx && (x - cx < 0 || x - cx >= nx)) ||
-                                   (wy && (y - cy < 0 || y - cy >= ny));
-              if (outside) v[k] = R(0);
-            }
-          }
           if (czi == 0) accum_group<R, -1>(v, accM);
           else if (czi == 1) accum_group<R, 0>(v, acc0);
           else accum_group<R, 1>(v, accP);
         }
-        // half-way bounce-back into this node (plane p)
+        // half-way bounce-back into this node (plane p): direction c pulls from
+        // behind a wall when the node is on that wall's side, and then takes
+        // the node's own post-collision population of direction -c
         if (wall_tile || zb_lo || zb_hi) {
+          uint32_t lw = lflags0;
+          asm volatile("" : "+v"(lw));
 #pragma unroll
           for (int czi = 0; czi < 3; ++czi) {
             const int cz = czi - 1;
@@ -492,12 +519,12 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
               const int cx = k % 3 - 1, cy = k / 3 - 1;
-              const bool outside = (wx && (x - cx < 0 || x - cx >= nx)) ||
-                                   (wy && (y - cy < 0 || y - cy >= ny));
+              const uint32_t m = (cx > 0 ? 4u : 0u) | (cx < 0 ? 8u : 0u) | (cy > 0 ? 16u : 0u) | (cy < 0 ? 32u : 0u);
+              const bool behind = zb || (lw & m) != 0u;
               R own;
               if (k == 4) own = fo[2 - czi];
               else own = sh.f[fslot(-cx, -cy, -cz) * NT + tid];
-              v[k] = (outside || zb) ? own : R(0);
+              v[k] = behind ? own : R(0);
             }
             if (czi == 0) accum_group<R, -1>(v, acc0);
             else if (czi == 1) accum_group<R, 0>(v, acc0);
@@ -581,14 +608,25 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 // ---------------------------------------------------------------------------
 // Non-hot kernels: encode / decode / observables / diagnostics
 // ---------------------------------------------------------------------------
+// element of field f (0 = phi, 1..10 = moments) at node i of a box
+__device__ __forceinline__ int64_t mom_index(const BoxDesc& b, int k, int64_t i) {
+  const int64_t plane = static_cast<int64_t>(b.nx) * b.ny;
+  const int64_t z = i / plane;
+  return (z * 10 + k) * plane + (i - z * plane);
+}
+
 template <class PR>
 __global__ void encode_kernel(BoxDesc b, int parity, int field, const double* __restrict__ src, int64_t n) {
   using TM = typename PR::TM;
   using TP = typename PR::TP;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    if (field == 0) static_cast<TP*>(b.fld[parity][0])[i] = Enc<TP>::go(src[i], 0.f, 1.f);
-    else static_cast<TM*>(b.fld[parity][field])[i] = Enc<TM>::go(src[i], b.enc_off[field], b.enc_scale[field]);
+    if (field == 0) {
+      ((gptr<TP>)b.phi[parity])[i] = Enc<TP>::go(src[i], 0.f, 1.f);
+    } else {
+      const int k = field - 1;
+      ((gptr<TM>)b.mom[parity])[mom_index(b, k, i)] = Enc<TM>::go(src[i], b.enc_off[k], b.enc_scale[k]);
+    }
   }
 }
 
@@ -598,8 +636,26 @@ __global__ void decode_kernel(BoxDesc b, int parity, int field, double* __restri
   using TP = typename PR::TP;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    if (field == 0) dst[i] = dec<double>(static_cast<const TP*>(b.fld[parity][0])[i], 0.f, 1.f);
-    else dst[i] = dec<double>(static_cast<const TM*>(b.fld[parity][field])[i], b.enc_off[field], b.enc_inv[field]);
+    if (field == 0) {
+      dst[i] = dec<double>(((gptr<const TP>)b.phi[parity])[i], 0.f, 1.f);
+    } else {
+      const int k = field - 1;
+      dst[i] = dec<double>(((gptr<const TM>)b.mom[parity])[mom_index(b, k, i)], b.enc_off[k], b.enc_inv[k]);
+    }
+  }
+}
+
+template <class PR>
+__global__ void gather_kernel(BoxDesc b, int parity, const int64_t* __restrict__ idx, int64_t n,
+                              double* __restrict__ out) {
+  using TM = typename PR::TM;
+  using TP = typename PR::TP;
+  for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < n;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t i = idx[j];
+    out[j] = dec<double>(((gptr<const TP>)b.phi[parity])[i], 0.f, 1.f);
+    for (int k = 0; k < 10; ++k)
+      out[(k + 1) * n + j] = dec<double>(((gptr<const TM>)b.mom[parity])[mom_index(b, k, i)], b.enc_off[k], b.enc_inv[k]);
   }
 }
 
@@ -612,12 +668,13 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
   using TP = typename PR::TP;
   const int nx = b.nx, ny = b.ny, nz = b.nz;
   const int64_t plane = static_cast<int64_t>(nx) * ny;
-  const TP* fphi = static_cast<const TP*>(b.fld[parity][0]);
+  const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
+  const gptr<const TM> fmom = (gptr<const TM>)b.mom[parity];
   double m[10];
   const int64_t idx = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
   finite = true;
   for (int k = 0; k < 10; ++k) {
-    m[k] = dec<double>(static_cast<const TM*>(b.fld[parity][k + 1])[idx], b.enc_off[k + 1], b.enc_inv[k + 1]);
+    m[k] = dec<double>(fmom[mom_index(b, k, idx)], b.enc_off[k], b.enc_inv[k]);
     finite = finite && isfinite(m[k]);
   }
   phi = dec<double>(fphi[idx], 0.f, 1.f);
@@ -769,31 +826,49 @@ int grid_for(int64_t n, int threads) {
   return static_cast<int>(g);
 }
 
+template <int BX, int BY, class PR>
+hipError_t launch_fused_t(const BoxDesc* d_boxes, const Item* d_items, int n_items, int grid, int parity,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL((fused_step<BX, BY, PR>), dim3(grid), dim3(BX * BY), 0, stream, d_boxes, d_items,
+                     n_items, parity);
+  return hipGetLastError();
+}
+
 template <int BX, int BY>
 hipError_t launch_fused_t(int precision, const BoxDesc* d_boxes, const Item* d_items, int n_items,
                           int grid, int parity, hipStream_t stream) {
   return dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
-    hipLaunchKernelGGL((fused_step<BX, BY, PR>), dim3(grid), dim3(BX * BY), 0, stream, d_boxes, d_items,
-                       n_items, parity);
-    return hipGetLastError();
+    return launch_fused_t<BX, BY, PR>(d_boxes, d_items, n_items, grid, parity, stream);
   });
 }
 
 }  // namespace
 
-bool fused_config_supported(int bx, int by) {
-  return (bx == 32 && by == 8) || (bx == 32 && by == 16) || (bx == 64 && by == 4) || (bx == 64 && by == 8);
+bool fused_config_supported(int precision, int bx, int by) {
+  if (bx == 66 && by == 8) return precision != kF64;  // FP64 needs > 168 VGPRs: would spill
+  return (bx == 32 && by == 8) || (bx == 34 && by == 8) || (bx == 34 && by == 15);
+}
+
+size_t phi_bytes(int precision, int64_t n) { return static_cast<size_t>(n) * (precision == kF64 ? 8 : 4); }
+size_t mom_bytes(int precision, int64_t n) {
+  const size_t e = precision == kF64 ? 8 : (precision == kF32 ? 4 : 2);
+  return static_cast<size_t>(n) * 10 * e;
 }
 
 hipError_t launch_fused(int precision, int bx, int by, const BoxDesc* d_boxes, const Item* d_items,
                         int n_items, int grid, int parity, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
+  if (!fused_config_supported(precision, bx, by)) return hipErrorInvalidValue;
   if (grid <= 0 || grid > n_items) grid = n_items;
   if (bx == 32 && by == 8) return launch_fused_t<32, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
-  if (bx == 32 && by == 16) return launch_fused_t<32, 16>(precision, d_boxes, d_items, n_items, grid, parity, stream);
-  if (bx == 64 && by == 4) return launch_fused_t<64, 4>(precision, d_boxes, d_items, n_items, grid, parity, stream);
-  if (bx == 64 && by == 8) return launch_fused_t<64, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 34 && by == 8) return launch_fused_t<34, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 34 && by == 15) return launch_fused_t<34, 15>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 66 && by == 8) {
+    if (precision == kF32) return launch_fused_t<66, 8, PF32>(d_boxes, d_items, n_items, grid, parity, stream);
+    if (precision == kF16) return launch_fused_t<66, 8, PF16>(d_boxes, d_items, n_items, grid, parity, stream);
+    return launch_fused_t<66, 8, PBF16>(d_boxes, d_items, n_items, grid, parity, stream);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -813,6 +888,16 @@ hipError_t launch_decode(int precision, const BoxDesc& box, int parity, int fiel
     using PR = decltype(pr);
     hipLaunchKernelGGL((decode_kernel<PR>), dim3(grid_for(n, 256)), dim3(256), 0, stream, box, parity, field,
                        d_dst, n);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_gather(int precision, const BoxDesc& box, int parity, const int64_t* d_idx, int64_t n,
+                         double* d_out, hipStream_t stream) {
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((gather_kernel<PR>), dim3(grid_for(n, 256)), dim3(256), 0, stream, box, parity, d_idx, n,
+                       d_out);
     return hipGetLastError();
   });
 }

@@ -14,7 +14,12 @@ constexpr int kFields = 11;  // phi, P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
 // Per-box constants and state pointers, resident in device memory; read with
 // uniform (scalar) loads by every workgroup working on the box.
 struct BoxDesc {
-  void* fld[2][kFields];  // ping-pong buffers: fld[parity][field]
+  // ping-pong state buffers, index = parity:
+  //   phi[s]: [nz][ny][nx] phase field (storage type of phi)
+  //   mom[s]: [nz][10][ny][nx] moments P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
+  //           (each z plane holds the 10 moment planes back to back)
+  void* phi[2];
+  void* mom[2];
   int32_t nx, ny, nz;
   int32_t wall[3];        // 1 if the axis has walls
   int32_t flags;          // LBM_LITERAL_ADVECTION
@@ -27,10 +32,10 @@ struct BoxDesc {
   double kappa_ac;        // 4 M / W
   double grav[3];
   double rho_ref;
-  float enc_off[kFields];   // stored = (v - off) * scale in 16-bit modes
-  float enc_scale[kFields];
-  float enc_inv[kFields];   // 1 / scale (exact: powers of two)
-  int32_t pad1;
+  float enc_off[10];      // moment k stored as (v - off) * scale in 16-bit modes
+  float enc_scale[10];
+  float enc_inv[10];      // 1 / scale (exact: powers of two)
+  int32_t pad1[2];
 };
 
 // One unit of work of the fused step: an output tile (x0, y0) of one box,
@@ -46,7 +51,11 @@ enum Precision { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 hipError_t launch_fused(int precision, int block_x, int block_y, const BoxDesc* d_boxes,
                         const Item* d_items, int n_items, int grid, int parity,
                         hipStream_t stream);
-bool fused_config_supported(int block_x, int block_y);
+bool fused_config_supported(int precision, int block_x, int block_y);
+
+// Bytes of the phi and moment arrays of one buffer of a box of n nodes.
+size_t phi_bytes(int precision, int64_t n);
+size_t mom_bytes(int precision, int64_t n);
 
 // Encode N doubles into field `field` (storage of `precision`).
 hipError_t launch_encode(int precision, const BoxDesc& box, int parity, int field,
@@ -54,6 +63,9 @@ hipError_t launch_encode(int precision, const BoxDesc& box, int parity, int fiel
 // Decode field `field` into N doubles.
 hipError_t launch_decode(int precision, const BoxDesc& box, int parity, int field,
                          double* d_dst, int64_t n, hipStream_t stream);
+// Gather the 11 decoded fields at n nodes: d_out[k*n + j] for node d_idx[j].
+hipError_t launch_gather(int precision, const BoxDesc& box, int parity, const int64_t* d_idx, int64_t n,
+                         double* d_out, hipStream_t stream);
 // Observable `which` (0 rho, 1 ux, 2 uy, 3 uz, 4 phi, 5 p) into N doubles.
 hipError_t launch_observable(int precision, const BoxDesc& box, int parity, int which,
                              double* d_dst, hipStream_t stream);

@@ -79,11 +79,6 @@ lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail((ctx), LBM_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-size_t storage_bytes(int precision, int field) {
-  if (precision == LBM_FP64) return 8;
-  if (precision == LBM_FP32) return 4;
-  return field == 0 ? 4 : 2;
-}
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
@@ -107,7 +102,7 @@ lbm_status validate_box(const lbm_params& p, int idx, int precision0) {
   if (p.lattice != LBM_D3Q27) return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: lattice %d unsupported (D3Q27 only)", who, idx, p.lattice);
   if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: dims must be >= 1", who, idx);
   if (p.nx > (1 << 20) || p.ny > (1 << 20) || p.nz > (1 << 20)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: dims must be <= 2^20", who, idx);
-  if (static_cast<int64_t>(p.nx) * p.ny > (int64_t(1) << 31)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: nx*ny must be <= 2^31", who, idx);
+  if (static_cast<int64_t>(p.nx) * p.ny > (int64_t(1) << 28)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: nx*ny must be <= 2^28", who, idx);
   const int d[3] = {p.nx, p.ny, p.nz};
   for (int a = 0; a < 3; ++a) {
     if (p.bc[a] != LBM_PERIODIC && p.bc[a] != LBM_WALL) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: bc[%d] = %d invalid", who, idx, a, p.bc[a]);
@@ -144,13 +139,10 @@ void fill_desc(Box& b, int precision) {
   for (int a = 0; a < 3; ++a) d.grav[a] = p.gravity[a];
   d.rho_ref = p.rho_ref;
   const bool os = precision == LBM_FP16_OS || precision == LBM_BF16_OS;
-  d.enc_off[0] = 0.f;
-  d.enc_scale[0] = 1.f;
-  d.enc_inv[0] = 1.f;
   for (int k = 0; k < 10; ++k) {
-    d.enc_off[k + 1] = os ? static_cast<float>(b.enc_off[k]) : 0.f;
-    d.enc_scale[k + 1] = os ? static_cast<float>(b.enc_scale[k]) : 1.f;
-    d.enc_inv[k + 1] = os ? static_cast<float>(1.0 / b.enc_scale[k]) : 1.f;
+    d.enc_off[k] = os ? static_cast<float>(b.enc_off[k]) : 0.f;
+    d.enc_scale[k] = os ? static_cast<float>(b.enc_scale[k]) : 1.f;
+    d.enc_inv[k] = os ? static_cast<float>(1.0 / b.enc_scale[k]) : 1.f;
   }
 }
 
@@ -336,16 +328,16 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
       b.prm = boxes[i];
       b.n = static_cast<int64_t>(b.prm.nx) * b.prm.ny * b.prm.nz;
       default_encoding(b);
-      size_t off[kFields + 1];
-      off[0] = 0;
-      for (int f = 0; f < kFields; ++f) off[f + 1] = off[f] + align256(b.n * storage_bytes(c->precision, f));
+      const size_t pb = align256(lbm::phi_bytes(c->precision, b.n));
+      const size_t total = pb + align256(lbm::mom_bytes(c->precision, b.n));
       for (int s = 0; s < 2; ++s) {
-        b.mem[s] = dev_alloc(c, off[kFields]);
+        b.mem[s] = dev_alloc(c, total);
         if (!b.mem[s]) {
           lbm_destroy(c);
-          return fail(nullptr, LBM_ERR_OOM, "lbm_create: state allocation of %zu bytes failed (box %d)", off[kFields], i);
+          return fail(nullptr, LBM_ERR_OOM, "lbm_create: state allocation of %zu bytes failed (box %d)", total, i);
         }
-        for (int f = 0; f < kFields; ++f) b.desc.fld[s][f] = static_cast<char*>(b.mem[s]) + off[f];
+        b.desc.phi[s] = b.mem[s];
+        b.desc.mom[s] = static_cast<char*>(b.mem[s]) + pb;
       }
     }
     c->d_boxes = static_cast<BoxDesc*>(dev_alloc(c, align256(n_boxes * sizeof(BoxDesc))));
@@ -354,16 +346,16 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
       lbm_destroy(c);
       return fail(nullptr, LBM_ERR_OOM, "lbm_create: descriptor allocation failed");
     }
-    // default tuning: 32 x 8 workgroups; z chunks short enough that the
-    // tile list fills the 256 CUs several times over
+    // default tuning: 34 x 8 workgroups (32 x 6 output columns); z chunks
+    // short enough that the tile list fills the 256 CUs several times over
     int zc = 64;
     for (; zc > 8; zc /= 2) {
       int64_t items = 0;
       for (auto& b : c->boxes)
-        items += static_cast<int64_t>((b.prm.nx + 29) / 30) * ((b.prm.ny + 5) / 6) * ((b.prm.nz + zc - 1) / zc);
+        items += static_cast<int64_t>((b.prm.nx + 31) / 32) * ((b.prm.ny + 5) / 6) * ((b.prm.nz + zc - 1) / zc);
       if (items >= 2048) break;
     }
-    c->tuning = lbm_tuning{32, 8, zc, 0};
+    c->tuning = lbm_tuning{34, 8, zc, 0};
     lbm_status s = upload_boxes(c);
     if (s == LBM_OK) s = build_items(c);
     if (s != LBM_OK) {
@@ -422,6 +414,26 @@ lbm_status lbm_get_state(lbm_ctx* c, int32_t box, double* state) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   if (!all_finite(state, kFields * b.n)) return fail(c, LBM_ERR_UNSTABLE, "lbm_get_state: non-finite state");
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state_points(lbm_ctx* c, int32_t box, int64_t n, const int64_t* node, double* out) {
+  lbm_status s = check_box(c, box);
+  if (s != LBM_OK) return s;
+  if (n < 0 || (n > 0 && (!node || !out))) return fail(c, LBM_ERR_ARG, "lbm_get_state_points: bad n / NULL arrays");
+  Box& b = c->boxes[box];
+  if (!b.initialized) return fail(c, LBM_ERR_STATE, "lbm_get_state_points: box %d not initialised", box);
+  for (int64_t j = 0; j < n; ++j)
+    if (node[j] < 0 || node[j] >= b.n) return fail(c, LBM_ERR_ARG, "lbm_get_state_points: node[%lld] out of range", static_cast<long long>(j));
+  if (n == 0) return LBM_OK;
+  // staging: n indices (as doubles' storage) + 11 n values
+  if ((s = ensure_stage(c, 12 * n)) != LBM_OK) return s;
+  int64_t* d_idx = reinterpret_cast<int64_t*>(c->d_stage);
+  double* d_out = c->d_stage + n;
+  HIP_TRY(c, hipMemcpyAsync(d_idx, node, n * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, lbm::launch_gather(c->precision, b.desc, c->parity, d_idx, n, d_out, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(out, d_out, 11 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 
@@ -538,7 +550,7 @@ lbm_status lbm_set_encoding(lbm_ctx* c, int32_t box, const double* offset, const
 lbm_status lbm_set_tuning(lbm_ctx* c, const lbm_tuning* t) {
   if (!c) return fail(nullptr, LBM_ERR_ARG, "NULL context");
   if (!t) return fail(c, LBM_ERR_ARG, "lbm_set_tuning: NULL tuning");
-  if (!lbm::fused_config_supported(t->block_x, t->block_y)) return fail(c, LBM_ERR_UNSUPPORTED, "lbm_set_tuning: block %dx%d unsupported", t->block_x, t->block_y);
+  if (!lbm::fused_config_supported(c->precision, t->block_x, t->block_y)) return fail(c, LBM_ERR_UNSUPPORTED, "lbm_set_tuning: block %dx%d unsupported for this precision", t->block_x, t->block_y);
   if (t->z_chunk < 1) return fail(c, LBM_ERR_ARG, "lbm_set_tuning: z_chunk must be >= 1");
   if (t->persistent < 0) return fail(c, LBM_ERR_ARG, "lbm_set_tuning: persistent must be >= 0");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -563,7 +575,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
   if (steps < 1) return fail(c, LBM_ERR_ARG, "lbm_autotune: steps must be >= 1");
   for (size_t i = 0; i < c->boxes.size(); ++i)
     if (!c->boxes[i].initialized) return fail(c, LBM_ERR_STATE, "lbm_autotune: box %zu not initialised", i);
-  const int shapes[4][2] = {{32, 8}, {32, 16}, {64, 4}, {64, 8}};
+  const int shapes[4][2] = {{32, 8}, {34, 8}, {34, 15}, {66, 8}};
   int maxz = 1;
   for (auto& b : c->boxes) maxz = std::max(maxz, b.prm.nz);
   std::vector<int> zcs;
@@ -578,6 +590,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
   const bool graphs = c->graphs;
   c->graphs = true;
   for (auto& sh : shapes) {
+    if (!lbm::fused_config_supported(c->precision, sh[0], sh[1])) continue;
     for (int zc : zcs) {
       lbm_tuning t{sh[0], sh[1], zc, 0};
       lbm_status s = lbm_set_tuning(c, &t);
@@ -612,9 +625,7 @@ lbm_status lbm_synchronize(lbm_ctx* c) {
 
 double lbm_bytes_per_update(const lbm_ctx* c) {
   if (!c) return 0.0;
-  double b = 0;
-  for (int f = 0; f < kFields; ++f) b += static_cast<double>(storage_bytes(c->precision, f));
-  return 2.0 * b;
+  return 2.0 * static_cast<double>(lbm::phi_bytes(c->precision, 1) + lbm::mom_bytes(c->precision, 1));
 }
 
 int64_t lbm_total_nodes(const lbm_ctx* c) {

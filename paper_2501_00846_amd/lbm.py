@@ -83,6 +83,8 @@ _SIGS = {
     "lbm_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(lbm_diag)]),
     "lbm_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "lbm_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "lbm_get_state_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_set_encoding": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "lbm_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(lbm_tuning)]),
@@ -199,6 +201,13 @@ def lbm_get_state(ctx, box, n):
     return st
 
 
+def lbm_get_state_points(ctx, box, nodes):
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.empty(11 * nodes.size)
+    _check(load_library().lbm_get_state_points(ctx, box, nodes.size, _ptr(nodes), _ptr(out)), ctx)
+    return out.reshape(11, nodes.size)
+
+
 def lbm_set_state(ctx, box, n, state):
     state = _f64(state, 11 * n)
     _check(load_library().lbm_set_state(ctx, box, _ptr(state)), ctx)
@@ -312,6 +321,13 @@ class Context:
     def get_state(self, box):
         p = self.problems[box]
         return lbm_get_state(self.ctx, box, self.sizes[box]).reshape(11, p.nz, p.ny, p.nx)
+
+    def state_at(self, box, points):
+        """11 decoded state values at (x, y, z) points -> (11, n)."""
+        p = self.problems[box]
+        pts = np.asarray(points, dtype=np.int64).reshape(-1, 3)
+        nodes = pts[:, 0] + p.nx * (pts[:, 1] + p.ny * pts[:, 2])
+        return lbm_get_state_points(self.ctx, box, nodes)
 
     def fields(self, box):
         p = self.problems[box]

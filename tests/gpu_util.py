@@ -55,3 +55,118 @@ def oracle_run_state(prob, state, nsteps):
     for _ in range(nsteps):
         st = S.step(st, prob)
     return state_array(st)
+
+
+# ---------------------------------------------------------------------------
+# Storage quantisation done on the host (never read back from the GPU): the
+# oracle starts from exactly the values the GPU stores at set_state / init.
+# ---------------------------------------------------------------------------
+DEFAULT_SCALE = np.array([1024.0] + [4096.0] * 3 + [65536.0] * 6)
+
+
+def _bf16_round(x32):
+    b = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    return (b.astype(np.uint32) << 16).view(np.float32)
+
+
+def quantize(values, precision, field):
+    """Stored-and-decoded value of `values` for field index (0 = phi, 1..10 moments)."""
+    v = np.asarray(values, dtype=np.float64)
+    if precision == "fp64":
+        return v.copy()
+    f32 = v.astype(np.float32)
+    if precision == "fp32" or field == 0:
+        return f32.astype(np.float64)
+    s = np.float32(DEFAULT_SCALE[field - 1])
+    if precision == "fp16_os":
+        return (f32 * s).astype(np.float16).astype(np.float32).astype(np.float64) / float(s)
+    if precision == "bf16_os":
+        return _bf16_round(f32 * s).astype(np.float64) / float(s)
+    raise ValueError(precision)
+
+
+def quantize_state(state, precision):
+    return np.stack([quantize(state[k], precision, k) for k in range(11)])
+
+
+# relative half-ulp of the storage format per field
+def storage_rel(precision, field):
+    if precision == "fp64":
+        return 2.0 ** -53
+    if precision == "fp32" or field == 0:
+        return 2.0 ** -24
+    return 2.0 ** -11 if precision == "fp16_os" else 2.0 ** -8
+
+
+class _Vec:
+    """Read-only (k, z, y, x) view built from per-component arrays (or None = 0)."""
+
+    def __init__(self, comps, shape):
+        self.comps = comps
+        self.shape = shape
+
+    def __getitem__(self, key):
+        rest = key[1:]
+        return np.array([0.0 if c is None else float(c[rest]) for c in self.comps])
+
+
+class _Ten:
+    def __init__(self, comps6, shape):
+        self.c = comps6
+
+    def __getitem__(self, key):
+        rest = key[2:]
+        q = [0.0 if c is None else float(c[rest]) for c in self.c]
+        return np.array([[q[0], q[3], q[4]], [q[3], q[1], q[5]], [q[4], q[5], q[2]]])
+
+
+class LazyState:
+    """Minimal State for the per-node oracle on big boxes: phi, P (arrays or
+    None), J (3 arrays or None), Q6 (6 arrays or None)."""
+
+    def __init__(self, phi, P=None, J=(None, None, None), Q6=(None,) * 6):
+        self.phi = phi
+        shape = phi.shape
+        self.P = P if P is not None else np.broadcast_to(np.float64(0.0), shape)
+        self.J = _Vec(list(J), shape)
+        self.Q = _Ten(list(Q6), shape)
+
+
+def sample_points(prob, rng, n_random=24, extra=()):
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    pts = set()
+    for c in [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (0, ny - 1, 0), (nx - 1, 0, nz - 1),
+              (nx // 2, ny // 2, 0), (nx // 2, ny // 2, 1), (nx // 2, ny // 2, nz - 1),
+              (nx // 2, ny // 2, nz - 2), (0, ny // 3, nz // 2), (nx - 1, ny // 3, nz // 2),
+              (nx // 3, 0, nz // 2), (nx // 3, ny - 1, nz // 2), (1, 1, 1)]:
+        pts.add(c)
+    for _ in range(n_random):
+        pts.add((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
+    for c in extra:
+        pts.add(tuple(int(v) for v in c))
+    return sorted(pts)
+
+
+def field_tolerance(precision, ref):
+    """Per-field absolute tolerance for one step from the same stored state.
+
+    FP64: 1e-12 of the field scale.  Reduced precision (FP32 arithmetic, FP64
+    only for rho, nu, omega): phi within 2e-5; every moment within 1e-5 of the
+    leading population scale max(|P|, |J|) -- each moment, Q included, is a
+    signed sum of populations of that size, and the chemical potential is a
+    near-cancelling difference whose FP32 rounding is amplified by 1/rho_g in
+    the light phase (measured up to 3e-6 of that scale for density ratio
+    1000) -- plus one storage half-ulp of the value.  ref may be (11, ...)."""
+    ref = np.asarray(ref)
+    tol = np.empty_like(ref)
+    s_mom = max(np.abs(ref[1]).max(), np.abs(ref[2:5]).max())
+    for k in range(11):
+        scale = np.abs(ref[k]).max()
+        if precision == "fp64":
+            tol[k] = 1e-12 * scale + 1e-300
+        elif k == 0:
+            tol[k] = 2e-5 * scale + 1.01 * storage_rel(precision, k) * np.abs(ref[k]) + 1e-300
+        else:
+            tol[k] = 1e-5 * max(scale, s_mom) + 1.01 * storage_rel(precision, k) * np.abs(ref[k]) + 1e-300
+    return tol
