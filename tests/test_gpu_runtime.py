@@ -147,8 +147,11 @@ def test_observables_and_diagnostics_match_oracle():
     for name in ("rho", "phi", "u", "p"):
         assert np.abs(f[name] - ob[name]).max() <= 1e-11 * np.abs(ob[name]).max(), name
     dg = S.diagnostics(array_state(st), prob)
+    # sums of signed values may cancel to ~0: absolute slack scales with the
+    # sum of magnitudes (summation order differs between GPU and NumPy)
+    abs_p = 1e-13 * np.abs(st[1]).sum()
     for key in ("phase_mass", "pstar_sum", "kinetic", "umax", "p_l", "p_g", "n_l", "n_g"):
-        assert d[key] == pytest.approx(dg[key], rel=1e-10, abs=1e-18), key
+        assert d[key] == pytest.approx(dg[key], rel=1e-10, abs=abs_p + 1e-30), key
     for key in ("momentum", "centroid_l", "velocity_l", "centroid_g", "velocity_g"):
         assert np.allclose(d[key], dg[key], rtol=1e-9, atol=1e-16), key
     assert d["nonfinite"] == 0
