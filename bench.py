@@ -79,7 +79,7 @@ def measured_traffic(config, precision, nodes):
     return ent["bytes_per_launch"]
 
 
-def run_mode(cases, precision, steps, warmup, tune, unbatched=False):
+def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None):
     import torch
 
     from paper_2501_00846_amd import lbm
@@ -87,7 +87,9 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False):
     ctx = lbm.Context([c.problem for c in cases], precision)
     for i, c in enumerate(cases):
         ctx.init_case(i, c)
-    if tune:
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
+    elif tune:
         ctx.autotune(steps=max(4, min(20, steps // 10)))
     step = ctx.step_unbatched if unbatched else ctx.step
     step(warmup)
@@ -149,6 +151,133 @@ def cpu_baseline(config):
             "kind": "oracle", "sample": sample, "seconds": round(dt, 2)}
 
 
+def _fields_and_diag(case, precision, steps, every=None):
+    from paper_2501_00846_amd import lbm
+
+    ctx = lbm.Context(case.problem, precision)
+    ctx.init_case(0, case)
+    trace = []
+    done = 0
+    every = every or steps
+    while done < steps:
+        k = min(every, steps - done)
+        ctx.step(k)
+        done += k
+        trace.append((done, ctx.diagnostics(0)))
+    f = ctx.fields(0)
+    ctx.close()
+    return f, trace
+
+
+def precision_study(args):
+    """Per-field error of each reduced-precision storage mode against the FP64
+    run of the same GPU path (itself pinned to the oracle), after N steps:
+    relative L2 and max norms of phi, rho, u, p; the Laplace pressure jump of
+    the static droplet; the rising bubble's centre-of-mass velocity."""
+    from paper_2501_00846_amd import workloads as WL
+
+    modes = ["fp32", "fp16_os", "bf16_os"]
+    studies = {
+        "C1": (WL.static_droplet(), 2000, "laplace"),
+        "C2": (WL.rising_bubble(), 2000, "ucom"),
+        "C3": (WL.droplet_collision(n=128, radius=12.0), 1000, None),
+    }
+    out = {}
+    for name, (case, steps, extra) in studies.items():
+        log("precision study %s: %d steps" % (name, steps))
+        ref, rtrace = _fields_and_diag(case, "fp64", steps, every=steps // 10)
+        res = {"steps": steps, "workload": case.name}
+        for m in modes:
+            got, gtrace = _fields_and_diag(case, m, steps, every=steps // 10)
+            errs = {}
+            for fld in ("phi", "rho", "u", "p"):
+                a, b = got[fld], ref[fld]
+                if fld == "u":
+                    for c, cn in enumerate("xyz"):
+                        da = a[c] - b[c]
+                        errs["u" + cn] = {"l2": float(np.linalg.norm(da) / max(np.linalg.norm(b[c]), 1e-300)),
+                                          "max": float(np.abs(da).max() / max(np.abs(b[c]).max(), 1e-300))}
+                    continue
+                d = a - b
+                errs[fld] = {"l2": float(np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300)),
+                             "max": float(np.abs(d).max() / max(np.abs(b).max(), 1e-300))}
+            if extra == "laplace":
+                dr = rtrace[-1][1]["p_l"] - rtrace[-1][1]["p_g"]
+                dg = gtrace[-1][1]["p_l"] - gtrace[-1][1]["p_g"]
+                errs["laplace_dp"] = {"fp64": dr, "mode": dg, "rel": abs(dg - dr) / abs(dr),
+                                      "vs_2sigma_over_R": dr / (2 * case.problem.sigma / 8.0)}
+            if extra == "ucom":
+                ur = np.array([t[1]["velocity_g"][2] for t in rtrace])
+                ug = np.array([t[1]["velocity_g"][2] for t in gtrace])
+                errs["u_com"] = {"fp64_final": float(ur[-1]), "mode_final": float(ug[-1]),
+                                 "rel_max_over_time": float(np.abs(ug - ur).max() / np.abs(ur).max())}
+            errs["phase_mass_drift"] = float((gtrace[-1][1]["phase_mass"] - rtrace[-1][1]["phase_mass"])
+                                             / rtrace[-1][1]["phase_mass"])
+            res[m] = errs
+            log("  %s: phi %.2e rho %.2e uz %.2e p %.2e (rel L2)" % (
+                m, errs["phi"]["l2"], errs["rho"]["l2"], errs["uz"]["l2"], errs["p"]["l2"]))
+        out[name] = res
+    print(json.dumps({"precision_study": out}), flush=True)
+
+
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written
+
+
+def copy_calibration(reps):
+    """A plain device copy of known size (torch's copy kernel), for scaling the
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)  # one elementwise kernel: 1 GiB read, 1 GiB written
+    torch.cuda.synchronize()
+    log("bench: copy calibration: %d copies of %d bytes" % (reps, COPY_BYTES))
+
+
+def _read_counter_csv(path, counter, name_part):
+    """Mean per-dispatch value (KiB as reported) of `counter` over dispatches whose
+    kernel name contains name_part, from a rocprofv3 counter_collection.csv."""
+    import csv
+
+    vals = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter or name_part not in row.get("Kernel_Name", ""):
+                continue
+            key = row.get("Dispatch_Id") or row.get("Correlation_Id")
+            vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
+    if not vals:
+        raise SystemExit("no %s rows for %s in %s" % (counter, name_part, path))
+    return sum(vals.values()) / len(vals)
+
+
+def summarize_counters(args):
+    """Turn four rocprofv3 --pmc runs (fused step FETCH_SIZE and WRITE_SIZE,
+    copy kernel FETCH_SIZE and WRITE_SIZE) into profiles/traffic.json."""
+    fetch = _read_counter_csv(args.fetch_csv, "FETCH_SIZE", "fused_step")
+    write = _read_counter_csv(args.write_csv, "WRITE_SIZE", "fused_step")
+    cf = _read_counter_csv(args.copy_fetch_csv, "FETCH_SIZE", args.copy_kernel)
+    cw = _read_counter_csv(args.copy_write_csv, "WRITE_SIZE", args.copy_kernel)
+    f_fetch = COPY_BYTES / (cf * 1024.0)
+    f_write = COPY_BYTES / (cw * 1024.0)
+    traffic = fetch * 1024.0 * f_fetch + write * 1024.0 * f_write
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    cases, _ = make_cases(args.config)
+    nodes = sum(c.problem.n_nodes for c in cases)
+    bpl = {"fp64": 176, "fp32": 88, "fp16_os": 48, "bf16_os": 48}[args.precision.split(",")[0]]
+    data["%s/%s" % (args.config, args.precision.split(",")[0])] = {
+        "kernel_hash": kernel_hash(), "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+        "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_fetch, "write_scale": f_write,
+        "bytes_per_launch": traffic, "nodes": nodes, "bytes_per_update_measured": traffic / nodes,
+        "bytes_per_update_algorithmic": bpl}
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    print(json.dumps(data["%s/%s" % (args.config, args.precision.split(",")[0])]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,7 +289,30 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--unbatched", action="store_true", help="C4: one launch per box per step")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="per-field errors of the reduced-precision modes against FP64")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
+                    help="only run REPS plain 1 GiB device copies (counter calibration)")
+    ap.add_argument("--summarize-counters", action="store_true",
+                    help="write profiles/traffic.json from rocprofv3 counter CSVs")
+    ap.add_argument("--fetch-csv")
+    ap.add_argument("--write-csv")
+    ap.add_argument("--copy-fetch-csv")
+    ap.add_argument("--copy-write-csv")
+    ap.add_argument("--copy-kernel", default="elementwise")
+    ap.add_argument("--tuning", default=None, metavar="BX,BY,ZCHUNK,PERSISTENT",
+                    help="fixed launch configuration instead of autotuning")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.precision_study:
+        precision_study(args)
+        return
+    if args.summarize_counters:
+        summarize_counters(args)
+        return
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the path is a single-GPU kernel; multi-GPU slab "
@@ -175,10 +327,18 @@ def main():
     modes = {}
     for prec in precisions:
         log("bench: %s %s: %d warmup + %d timed steps" % (args.config, prec, args.warmup, args.steps))
-        modes[prec] = run_mode(cases, prec, args.steps, args.warmup, not args.no_tune, args.unbatched)
+        tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+        modes[prec] = run_mode(cases, prec, args.steps, args.warmup, not args.no_tune, args.unbatched, tuning)
         log("bench: %s %s: %.0f MLUPS, kernel %.3f ms/step, %.0f GB/s (%.1f%% of HBM peak)" % (
             args.config, prec, modes[prec]["mlups"], modes[prec]["kernel_ms"], modes[prec]["achieved_gbs"],
             100 * modes[prec]["frac"]))
+    if args.config == "C4" and not args.unbatched:
+        # the unbatched baseline: one launch per box per step (no graphs)
+        prec = precisions[0]
+        log("bench: C4 %s unbatched baseline" % prec)
+        modes[prec + "_unbatched"] = run_mode(cases, prec, args.steps, args.warmup, False, True,
+                                              tuple(modes[prec]["tuning"].values()))
+        log("bench: C4 unbatched: %.0f MLUPS" % modes[prec + "_unbatched"]["mlups"])
     head = precisions[0]
     m = modes[head]
     traffic = measured_traffic(args.config, head, m["nodes"])

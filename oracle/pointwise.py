@@ -64,14 +64,13 @@ class PointOracle:
         phi = st.phi[z, y, x]
         gphi = np.zeros(3)
         lap = 0.0
-        grho = np.zeros(3)
         rho_c = scheme.density(phi, prob)
         for i in range(NQ):
             cx, cy, cz = (int(v) for v in C[i])
             pn = self.phi_at(x + cx, y + cy, z + cz)
             gphi += (W[i] / CS2) * pn * C[i]
             lap += (2.0 * W[i] / CS2) * (pn - phi)
-            grho += (W[i] / CS2) * scheme.density(pn, prob) * C[i]
+        grho = scheme.density_gradient(gphi, prob)
         P = st.P[z, y, x]
         J = st.J[:, z, y, x].copy()
         Qt = st.Q[:, :, z, y, x].copy()

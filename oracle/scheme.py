@@ -60,6 +60,13 @@ the design notes of the repository):
       when rho_ref is the liquid density).
   R13 Phase-field time level: all terms at level n (explicit Euler), computed
       from the same node quantities the flow step uses.
+  R14 The material laws rho(phi) and nu(phi) are evaluated at phi clamped to
+      [0, 1], the range the model assigns to phi (Sec. II.A); the density
+      gradient in the pressure and viscous corrections is the derivative of
+      the linear law, (rho_l - rho_g) grad(phi).  FTCS advection at cell
+      Peclet number u/M > 2 over- and undershoots slightly; unclamped, an
+      undershoot below -rho_g/(rho_l - rho_g) makes rho <= 0 at density ratio
+      1000 and an overshoot can make nu < 0.
 """
 from __future__ import annotations
 
@@ -183,14 +190,27 @@ def divergence(vp, h, e=0):
 # Local (per node) physics; every function broadcasts over node arrays
 # ----------------------------------------------------------------------------
 
+def clamp01(phi):
+    """phi restricted to the model's range [0, 1] (reading R14)."""
+    return np.minimum(np.maximum(phi, 0.0), 1.0)
+
+
 def density(phi, prob):
-    """rho = rho_l phi + (1 - phi) rho_g  (Sec. II.C, below Eq. press_corr)."""
+    """rho = rho_l phi + (1 - phi) rho_g  (Sec. II.C, below Eq. press_corr),
+    at phi clamped to [0, 1] (R14)."""
+    phi = clamp01(phi)
     return prob.rho_l * phi + (1.0 - phi) * prob.rho_g
 
 
+def density_gradient(grad_phi, prob):
+    """grad(rho) = (rho_l - rho_g) grad(phi): derivative of the linear law (R14)."""
+    return (prob.rho_l - prob.rho_g) * grad_phi
+
+
 def viscosity(phi, prob):
-    """Reading R8: linear interpolation of the kinematic viscosity."""
-    return prob.nu_g + phi * (prob.nu_l - prob.nu_g)
+    """Reading R8: linear interpolation of the kinematic viscosity, at phi
+    clamped to [0, 1] (R14)."""
+    return prob.nu_g + clamp01(phi) * (prob.nu_l - prob.nu_g)
 
 
 def relaxation(nu):
@@ -300,7 +320,7 @@ def node_fields(st, prob):
     gphi = grad(phip, 2)
     lphi = laplacian(phip, 2)
     rho = density(st.phi, prob)
-    grho = grad(pad(rho, prob, 1), 1)
+    grho = density_gradient(gphi, prob)
     nu = viscosity(st.phi, prob)
     om = relaxation(nu)
     F = total_force(st.phi, gphi, lphi, grho, st.P, st.Q, prob)

@@ -181,8 +181,14 @@ struct FusedShared {
 // ---------------------------------------------------------------------------
 // The fused step
 // ---------------------------------------------------------------------------
+// Occupancy targets: FP64 needs ~235 VGPRs (2 waves per SIMD); the FP32
+// arithmetic instantiations are held to 128 VGPRs for 4 waves per SIMD (the
+// few spills this costs sit outside the z loop).
+template <class PR> struct WavesPerEU { static constexpr int v = 4; };
+template <> struct WavesPerEU<PF64> { static constexpr int v = 2; };
+
 template <int BX, int BY, class PR>
-__global__ void __launch_bounds__(BX * BY)
+__global__ void __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(WavesPerEU<PR>::v)))
 fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, int n_items,
            int parity) {
   using TM = typename PR::TM;
@@ -249,13 +255,24 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const int i = e % PX, jj = e / PX;
       phcol[j] = static_cast<uint32_t>(map_axis(item.y0 - 2 + jj, ny, wy) * nx + map_axis(item.x0 - 2 + i, nx, wx));
     }
-    auto stage_phi = [&](int q) {
+    // phi of one plane at this thread's halo elements: loaded one plane ahead
+    // into registers, stored to LDS when the plane is needed
+    auto load_phi = [&](int q, R* v) {
       const gptr<const TP> src = s_phi_g + static_cast<int64_t>(map_plane(q, nz, wz)) * plane;
+#pragma unroll
+      for (int j = 0; j < NPH; ++j) v[j] = static_cast<R>(src[phcol[j]]);
+    };
+    auto store_phi = [&](const R* v) {
 #pragma unroll
       for (int j = 0; j < NPH; ++j) {
         const int e = tid + j * NT;
-        if (j < NPH - 1 || e < PX * PY) sh.phi[e] = static_cast<R>(src[phcol[j]]);
+        if (j < NPH - 1 || e < PX * PY) sh.phi[e] = v[j];
       }
+    };
+    auto stage_phi = [&](int q) {
+      R v[NPH];
+      load_phi(q, v);
+      store_phi(v);
     };
     // returns (A', Bx', By', phi_c): A' = s_x s_y phi, Bx' = s_y d_x phi,
     // By' = s_x d_y phi with s = (1,4,1), d = (-1,0,1)
@@ -297,6 +314,8 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       }
     };
     load_moments(p_first, nxt);
+    R phinxt[NPH];
+    load_phi(p_first + 1, phinxt);
 
     Acc<R> accM, acc0, accP;
     accM.zero();
@@ -330,8 +349,9 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       for (int k = 0; k < 10; ++k) cur[k] = nxt[k];
       if (p < p_last) load_moments(p + 1, nxt);
 
-      // (A) phi plane p+1 -> LDS -> filtered registers
-      stage_phi(p + 1);
+      // (A) phi plane p+1 (prefetched) -> LDS -> filtered registers; prefetch p+2
+      store_phi(phinxt);
+      if (p < p_last) load_phi(p + 2, phinxt);
       __syncthreads();
       filter_phi(Fp);
 
@@ -352,8 +372,9 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R Jx = cur[1], Jy = cur[2], Jz = cur[3];
       const R Qxx = cur[4], Qyy = cur[5], Qzz = cur[6], Qxy = cur[7], Qxz = cur[8], Qyz = cur[9];
 
-      // density, viscosity and relaxation interpolation in FP64 (Sec. II.C)
-      const double phid = static_cast<double>(phi);
+      // density, viscosity and relaxation interpolation in FP64 (Sec. II.C),
+      // evaluated at phi clamped to the model's range [0, 1]
+      const double phid = fmin(fmax(static_cast<double>(phi), 0.0), 1.0);
       const double rho = b.rho_g + phid * b.drho;
       const double inv_rho = 1.0 / rho;
       const double nu = b.nu_g + phid * b.dnu;
@@ -693,8 +714,9 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
         g[2] += 3.0 * w * cz * v;
         lap += 6.0 * w * (v - phi);
       }
-  rho = b.rho_g + phi * b.drho;
-  const double nu = b.nu_g + phi * b.dnu;
+  const double phic = fmin(fmax(phi, 0.0), 1.0);
+  rho = b.rho_g + phic * b.drho;
+  const double nu = b.nu_g + phic * b.dnu;
   const double om = 1.0 / (3.0 * nu + 0.5);
   const double mu = b.beta4 * phi * (phi - 1.0) * (phi - 0.5) - b.kappa_mu * lap;
   const double P = m[0];

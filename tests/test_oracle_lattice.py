@@ -182,3 +182,19 @@ def test_chemical_potential_zero_on_profile():
     assert sig == pytest.approx(prob.sigma, rel=1e-7)
     ac = prob.mobility * dphi - (4 * prob.mobility / W) * phi * (1 - phi)
     assert np.max(np.abs(ac)) < 1e-16
+
+
+def test_material_laws_clamped_to_phase_range():
+    """Reading R14: rho(phi) and nu(phi) use phi clamped to [0, 1], so an
+    FTCS undershoot cannot make rho <= 0 (density ratio 1000) or nu < 0;
+    inside [0, 1] they are the linear laws of Sec. II.C."""
+    prob = Problem(1, 1, 1, rho_l=1.0, rho_g=1e-3, nu_l=1 / 60, nu_g=1 / 6)
+    phi = np.array([-0.01, -1e-3, 0.0, 0.25, 1.0, 1.05, 1.2])
+    rho = S.density(phi, prob)
+    nu = S.viscosity(phi, prob)
+    assert (rho > 0).all() and (nu > 0).all()
+    assert rho[0] == prob.rho_g and rho[-1] == prob.rho_l
+    assert rho[3] == pytest.approx(0.25 * 1.0 + 0.75 * 1e-3, rel=1e-15)
+    assert nu[3] == pytest.approx(1 / 6 + 0.25 * (1 / 60 - 1 / 6), rel=1e-15)
+    g = np.array([0.1, -0.2, 0.3])
+    assert np.allclose(S.density_gradient(g, prob), (1.0 - 1e-3) * g, rtol=1e-15)
