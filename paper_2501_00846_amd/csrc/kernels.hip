@@ -120,6 +120,14 @@ __device__ __forceinline__ int map_axis(int i, int n, int wall) {
   return map_axis(i, n, wall, c);
 }
 
+// 1 / (sqrt(s) + 1e-12): IEEE sqrt and division in FP64; in FP32 the
+// hardware square root and reciprocal (about 1 ulp), which the FP32 modes'
+// error budget absorbs.
+__device__ __forceinline__ double inv_norm_eps(double s) { return 1.0 / (sqrt(s) + 1e-12); }
+__device__ __forceinline__ float inv_norm_eps(float s) {
+  return __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(s) + 1e-12f);
+}
+
 // Plane index map for a uniform q in [-2, n+1]: fast path inside the domain.
 __device__ __forceinline__ int map_plane(int q, int n, int wall) {
   if (q >= 0 && q < n) return q;
@@ -376,9 +384,11 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       // evaluated at phi clamped to the model's range [0, 1]
       const double phid = fmin(fmax(static_cast<double>(phi), 0.0), 1.0);
       const double rho = b.rho_g + phid * b.drho;
-      const double inv_rho = 1.0 / rho;
       const double nu = b.nu_g + phid * b.dnu;
-      const double om_d = 1.0 / (3.0 * nu + 0.5);
+      const double tau = 3.0 * nu + 0.5;        // 1 / omega
+      const double r_rt = 1.0 / (rho * tau);    // one division for 1/rho and omega
+      const double inv_rho = tau * r_rt;
+      const double om_d = rho * r_rt;
       const double bfac = 1.0 - b.rho_ref * inv_rho;  // body acceleration factor
       const R om1 = static_cast<R>(1.0 - om_d);
       const R irho = static_cast<R>(inv_rho);
@@ -480,8 +490,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 
       // phase-field flux G at this node (ghost rules on mirrored columns)
       {
-        const R gm = sqrt(gx * gx + gy * gy + gz * gz) + R(1e-12);
-        const R ig = R(1) / gm;
+        const R ig = inv_norm_eps(gx * gx + gy * gy + gz * gz);  // 1 / (|grad phi| + 1e-12)
         const R sharp = kappa_ac * phi * (R(1) - phi) * ig;
         const R us = (gcx != gcy) ? R(-1) : R(1);
         const R pu = literal ? R(0) : phi * us;
