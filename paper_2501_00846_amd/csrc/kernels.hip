@@ -325,6 +325,18 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     R phinxt[NPH];
     load_phi(p_first + 1, phinxt);
 
+    // Prefetched registers are consumed here, before this plane's global
+    // stores are issued: loads and stores retire through one in-order vector
+    // memory counter, so a wait placed after the stores (where the compiler
+    // would put it, at the copy into next plane's registers) also waits for
+    // every store.
+    auto settle_prefetch = [&]() {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) asm volatile("" ::"v"(nxt[k]));
+#pragma unroll
+      for (int j = 0; j < NPH; ++j) asm volatile("" ::"v"(phinxt[j]));
+    };
+
     Acc<R> accM, acc0, accP;
     accM.zero();
     acc0.zero();
@@ -508,6 +520,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         }
       }
       const R adv_own = literal ? (ux * gmx + uy * gmy + uz * gz) : R(0);
+      settle_prefetch();
       // ghost columns contribute no regular pulls: the populations that would
       // stream out of them are replaced by bounce-back at the wall node
       if (wall_tile && (gcx || gcy)) {
