@@ -878,6 +878,24 @@ hipError_t launch_fused_t(const BoxDesc* d_boxes, const Item* d_items, int n_ite
   return hipGetLastError();
 }
 
+template <int BX, int BY, class PR>
+int fused_blocks_per_cu_t() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_step<BX, BY, PR>, BX * BY, 0) != hipSuccess) return 0;
+  return n;
+}
+
+template <int BX, int BY>
+int fused_blocks_per_cu_t(int precision) {
+  switch (precision) {
+    case kF64: return fused_blocks_per_cu_t<BX, BY, PF64>();
+    case kF32: return fused_blocks_per_cu_t<BX, BY, PF32>();
+    case kF16: return fused_blocks_per_cu_t<BX, BY, PF16>();
+    case kBF16: return fused_blocks_per_cu_t<BX, BY, PBF16>();
+    default: return 0;
+  }
+}
+
 template <int BX, int BY>
 hipError_t launch_fused_t(int precision, const BoxDesc* d_boxes, const Item* d_items, int n_items,
                           int grid, int parity, hipStream_t stream) {
@@ -898,6 +916,16 @@ size_t phi_bytes(int precision, int64_t n) { return static_cast<size_t>(n) * (pr
 size_t mom_bytes(int precision, int64_t n) {
   const size_t e = precision == kF64 ? 8 : (precision == kF32 ? 4 : 2);
   return static_cast<size_t>(n) * 10 * e;
+}
+
+int fused_blocks_per_cu(int precision, int bx, int by) {
+  if (!fused_config_supported(precision, bx, by)) return 0;
+  if (bx == 32 && by == 8) return fused_blocks_per_cu_t<32, 8>(precision);
+  if (bx == 34 && by == 8) return fused_blocks_per_cu_t<34, 8>(precision);
+  if (bx == 34 && by == 15) return fused_blocks_per_cu_t<34, 15>(precision);
+  if (precision == kF32) return fused_blocks_per_cu_t<66, 8, PF32>();
+  if (precision == kF16) return fused_blocks_per_cu_t<66, 8, PF16>();
+  return fused_blocks_per_cu_t<66, 8, PBF16>();
 }
 
 hipError_t launch_fused(int precision, int bx, int by, const BoxDesc* d_boxes, const Item* d_items,

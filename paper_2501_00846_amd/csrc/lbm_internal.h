@@ -52,6 +52,8 @@ hipError_t launch_fused(int precision, int block_x, int block_y, const BoxDesc* 
                         const Item* d_items, int n_items, int grid, int parity,
                         hipStream_t stream);
 bool fused_config_supported(int precision, int block_x, int block_y);
+// Workgroups of the fused kernel that fit on one compute unit at once (0 on error).
+int fused_blocks_per_cu(int precision, int block_x, int block_y);
 
 // Bytes of the phi and moment arrays of one buffer of a box of n nodes.
 size_t phi_bytes(int precision, int64_t n);

@@ -286,6 +286,22 @@ bool all_finite(const double* v, int64_t n) {
   return true;
 }
 
+// Smallest z-chunk whose tile list fits in `slots` resident workgroups, so that
+// the launch runs in whole rounds of the device instead of ending on a
+// partly filled one; 0 if no chunk up to maxz does.
+int wave_balanced_chunk(const lbm_ctx* c, int tx, int ty, int64_t slots, int maxz) {
+  for (int zc = 1; zc <= maxz; ++zc) {
+    int64_t items = 0;
+    for (auto& b : c->boxes) {
+      const lbm_params& p = b.prm;
+      const int64_t cols = static_cast<int64_t>((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty);
+      items += cols * ((p.nz + std::min(zc, p.nz) - 1) / std::min(zc, p.nz));
+    }
+    if (items <= slots) return zc;
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -578,10 +594,13 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
   const int shapes[4][2] = {{32, 8}, {34, 8}, {34, 15}, {66, 8}};
   int maxz = 1;
   for (auto& b : c->boxes) maxz = std::max(maxz, b.prm.nz);
-  std::vector<int> zcs;
+  std::vector<int> fixed_zcs;
   for (int z : {8, 16, 32, 64, 128})
-    if (z <= maxz) zcs.push_back(z);
-  if (zcs.empty() || zcs.back() < maxz) zcs.push_back(maxz);
+    if (z <= maxz) fixed_zcs.push_back(z);
+  if (fixed_zcs.empty() || fixed_zcs.back() < maxz) fixed_zcs.push_back(maxz);
+  int dev = 0, cus = 0;
+  HIP_TRY(c, hipGetDevice(&dev));
+  HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
@@ -591,6 +610,12 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
   c->graphs = true;
   for (auto& sh : shapes) {
     if (!lbm::fused_config_supported(c->precision, sh[0], sh[1])) continue;
+    std::vector<int> zcs = fixed_zcs;
+    const int slots = cus * lbm::fused_blocks_per_cu(c->precision, sh[0], sh[1]);
+    for (int rounds = 1; slots > 0 && rounds <= 4; ++rounds) {
+      const int zc = wave_balanced_chunk(c, sh[0] - 2, sh[1] - 2, static_cast<int64_t>(rounds) * slots, maxz);
+      if (zc >= 4 && std::find(zcs.begin(), zcs.end(), zc) == zcs.end()) zcs.push_back(zc);
+    }
     for (int zc : zcs) {
       lbm_tuning t{sh[0], sh[1], zc, 0};
       lbm_status s = lbm_set_tuning(c, &t);
