@@ -65,9 +65,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(config, precision, nodes):
+def measured_traffic(config, precision, tuning):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source at the same tile shape and z-chunk;
+    else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -76,7 +77,33 @@ def measured_traffic(config, precision, nodes):
     ent = data.get("%s/%s" % (config, precision))
     if not ent or ent.get("kernel_hash") != kernel_hash():
         return None
+    launch = [tuning[k] for k in ("block_x", "block_y", "z_chunk")]
+    if ent.get("tuning") is not None and ent["tuning"][:3] != launch:
+        return None
     return ent["bytes_per_launch"]
+
+
+def copy_bandwidth(nbytes=1 << 31, reps=10):
+    """Device-to-device copy rate (GB/s, bytes read + written) of torch's copy
+    kernel on the current stream: the attainable-bandwidth reference beside the
+    8 TB/s specification."""
+    import torch
+
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None):
@@ -268,8 +295,10 @@ def summarize_counters(args):
     cases, _ = make_cases(args.config)
     nodes = sum(c.problem.n_nodes for c in cases)
     bpl = {"fp64": 176, "fp32": 88, "fp16_os": 48, "bf16_os": 48}[args.precision.split(",")[0]]
+    tuning = [int(v) for v in args.tuning.split(",")] if args.tuning else None
     data["%s/%s" % (args.config, args.precision.split(",")[0])] = {
-        "kernel_hash": kernel_hash(), "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+        "kernel_hash": kernel_hash(), "tuning": tuning,
+        "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
         "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_fetch, "write_scale": f_write,
         "bytes_per_launch": traffic, "nodes": nodes, "bytes_per_update_measured": traffic / nodes,
         "bytes_per_update_algorithmic": bpl}
@@ -341,9 +370,12 @@ def main():
         log("bench: C4 unbatched: %.0f MLUPS" % modes[prec + "_unbatched"]["mlups"])
     head = precisions[0]
     m = modes[head]
-    traffic = measured_traffic(args.config, head, m["nodes"])
+    traffic = measured_traffic(args.config, head, m["tuning"])
+    copy_gbs = copy_bandwidth()
+    log("bench: device copy %.0f GB/s" % copy_gbs)
     roof = {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(m["frac"], 4), "traffic": traffic,
+            "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(m["achieved_gbs"] / copy_gbs, 4),
             "kernel": "fused_step (%s)" % head, "bytes_per_update": m["bytes_per_update"],
             "nodes_per_launch": m["nodes"]}
     cpu = None

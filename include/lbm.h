@@ -126,7 +126,7 @@ typedef struct {
 
 /* Tile / launch configuration of the fused step (chosen by lbm_autotune). */
 typedef struct {
-  int32_t block_x, block_y; /* workgroup columns; supported pairs: (32,8) (34,8) (34,15), and (66,8) except in FP64 */
+  int32_t block_x, block_y; /* workgroup columns; supported pairs: (32,8) (34,8) (34,15) (18,14), and (66,8) except in FP64 */
   int32_t z_chunk;          /* planes marched by one workgroup, >= 1 */
   int32_t persistent;       /* 0: one workgroup per tile; n > 0: n workgroups loop over tiles */
 } lbm_tuning;

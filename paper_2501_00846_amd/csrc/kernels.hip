@@ -128,6 +128,25 @@ __device__ __forceinline__ float inv_norm_eps(float s) {
   return __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(s) + 1e-12f);
 }
 
+// A wave-uniform address, pinned to scalar registers and opaque to the
+// optimiser, so that a load or store at base + 32-bit lane offset is issued in
+// the scalar-base form (no per-lane 64-bit address arithmetic) instead of being
+// strength-reduced into per-lane pointer increments.
+template <class T>
+__device__ __forceinline__ gptr<T> sbase(gptr<T> p) {
+  uint64_t a = reinterpret_cast<uint64_t>(p);
+  asm("" : "+s"(a));
+  return reinterpret_cast<gptr<T>>(a);
+}
+
+// A per-lane 32-bit byte offset, re-materialised where it is used so that its
+// zero extension is visible next to the access (instruction selection matches
+// the scalar-base form only within one basic block).
+__device__ __forceinline__ uint32_t lane_off(uint32_t v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 // Plane index map for a uniform q in [-2, n+1]: fast path inside the domain.
 __device__ __forceinline__ int map_plane(int q, int n, int wall) {
   if (q >= 0 && q < n) return q;
@@ -176,6 +195,37 @@ __device__ __forceinline__ void accum_group(const R* v, Acc<R>& a) {
   }
 }
 
+// Lane -> tile position (tx, ty).  When the output rows are a multiple of 32
+// columns wide, the (BX-2) x (BY-2) output columns come first, row by row:
+// every wavefront then covers whole, aligned output rows, so its loads and
+// stores of a field are full memory segments (each partial segment costs the
+// vector L1 a request of its own, and stores are limited by those requests).
+// The halo ring follows: top row, bottom row, left column, right column.
+// Other shapes keep the row-major order of the block.
+template <int BX, int BY>
+__device__ __forceinline__ void lane_position(int tid, int& tx, int& ty) {
+  constexpr int IX = BX - 2, IY = BY - 2, NI = IX * IY;
+  if constexpr (IX % 32 != 0) {
+    tx = tid % BX;
+    ty = tid / BX;
+    return;
+  }
+  if (tid < NI) {
+    ty = tid / IX + 1;
+    tx = tid % IX + 1;
+    return;
+  }
+  int h = tid - NI;
+  if (h < BX) { tx = h; ty = 0; return; }
+  h -= BX;
+  if (h < BX) { tx = h; ty = BY - 1; return; }
+  h -= BX;
+  if (h < IY) { tx = 0; ty = h + 1; return; }
+  h -= IY;
+  tx = BX - 1;
+  ty = h + 1;
+}
+
 template <int BX, int BY, class PR>
 struct FusedShared {
   using R = typename PR::R;
@@ -208,8 +258,9 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
   __shared__ FusedShared<BX, BY, PR> sh;
 
   const int tid = threadIdx.x;
-  const int tx = tid % BX;
-  const int ty = tid / BX;
+  int tx, ty;
+  lane_position<BX, BY>(tid, tx, ty);
+  const int sp = ty * BX + tx;  // LDS slot of this thread's tile position
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const Item item = items[it];
@@ -242,6 +293,10 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     const gptr<TP> d_phi_g = (gptr<TP>)(b.phi[1 - parity]);
     const gptr<TM> d_mom = (gptr<TM>)(b.mom[1 - parity]);
     const uint32_t ucol = static_cast<uint32_t>(col);
+    const uint32_t voff_p = ucol * static_cast<uint32_t>(sizeof(TP));  // byte offset in a phi plane
+    const uint32_t voff_m = ucol * static_cast<uint32_t>(sizeof(TM));  // byte offset in a moment plane
+    const int64_t plane_bp = plane * static_cast<int64_t>(sizeof(TP));
+    const int64_t plane_bm = plane * static_cast<int64_t>(sizeof(TM));
 
     const R beta4 = static_cast<R>(b.beta4);
     const R kappa_mu = static_cast<R>(b.kappa_mu);
@@ -261,14 +316,18 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     for (int j = 0; j < NPH; ++j) {
       const int e = tid + j * NT;
       const int i = e % PX, jj = e / PX;
-      phcol[j] = static_cast<uint32_t>(map_axis(item.y0 - 2 + jj, ny, wy) * nx + map_axis(item.x0 - 2 + i, nx, wx));
+      phcol[j] = static_cast<uint32_t>(map_axis(item.y0 - 2 + jj, ny, wy) * nx + map_axis(item.x0 - 2 + i, nx, wx)) *
+                 static_cast<uint32_t>(sizeof(TP));
     }
     // phi of one plane at this thread's halo elements: loaded one plane ahead
-    // into registers, stored to LDS when the plane is needed
+    // into registers, stored to LDS when the plane is needed.  Addresses are a
+    // uniform plane base plus a 32-bit per-lane byte offset (a plane holds at
+    // most 2^28 nodes, so offsets within it fit), which keeps the per-load
+    // address arithmetic off the vector ALUs.
     auto load_phi = [&](int q, R* v) {
-      const gptr<const TP> src = s_phi_g + static_cast<int64_t>(map_plane(q, nz, wz)) * plane;
+      const gptr<const char> src = sbase((gptr<const char>)s_phi_g + static_cast<int64_t>(map_plane(q, nz, wz)) * plane_bp);
 #pragma unroll
-      for (int j = 0; j < NPH; ++j) v[j] = static_cast<R>(src[phcol[j]]);
+      for (int j = 0; j < NPH; ++j) v[j] = static_cast<R>(*(gptr<const TP>)(src + lane_off(phcol[j])));
     };
     auto store_phi = [&](const R* v) {
 #pragma unroll
@@ -311,15 +370,11 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 
     // moments of the own column, prefetched one plane ahead
     R nxt[10];
-    const uint32_t uplane = static_cast<uint32_t>(plane);
     auto load_moments = [&](int q, R* m) {
-      const gptr<const TM> base = s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * 10 * plane;
-      uint32_t off = ucol;
+      const gptr<const char> base = (gptr<const char>)s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * 10 * plane_bm;
 #pragma unroll
-      for (int k = 0; k < 10; ++k) {
-        m[k] = dec<R>(base[off], b.enc_off[k], b.enc_inv[k]);
-        off += uplane;
-      }
+      for (int k = 0; k < 10; ++k)
+        m[k] = dec<R>(*(gptr<const TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), b.enc_off[k], b.enc_inv[k]);
     };
     load_moments(p_first, nxt);
     R phinxt[NPH];
@@ -337,6 +392,13 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       for (int j = 0; j < NPH; ++j) asm volatile("" ::"v"(phinxt[j]));
     };
 
+    // The loop header joins this path with the back edge, where the prefetched
+    // registers are already settled; settling them here too keeps the
+    // compiler from placing a wait for them at the top of every iteration,
+    // which (counting in order) would also wait for the previous plane's
+    // stores.
+    settle_prefetch();
+
     Acc<R> accM, acc0, accP;
     accM.zero();
     acc0.zero();
@@ -344,7 +406,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     R phiH = R(0), lapH = R(0), advH = R(0);  // own-node phi, lap(phi), u.grad(phi) of plane p-1
 
     auto finalize = [&](int Z, const Acc<R>& a, R d, R phic, R lapc, R advc) {
-      const gptr<TM> base = d_mom + static_cast<int64_t>(Z) * 10 * plane;
+      const gptr<char> base = (gptr<char>)d_mom + static_cast<int64_t>(Z) * 10 * plane_bm;
       const R P = a.p;
       const R q_xx = a.xx - P * R(1.0 / 3.0) - a.jx * a.jx;
       const R q_yy = a.yy - P * R(1.0 / 3.0) - a.jy * a.jy;
@@ -353,14 +415,11 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R q_xz = a.xz - a.jx * a.jz;
       const R q_yz = a.yz - a.jy * a.jz;
       const R phin = phic + mob * lapc - advc - d * R(1.0 / 72.0);
-      d_phi_g[static_cast<int64_t>(Z) * plane + ucol] = Enc<TP>::go(phin, 0.f, 1.f);
+      *(gptr<TP>)(sbase((gptr<char>)d_phi_g + static_cast<int64_t>(Z) * plane_bp) + lane_off(voff_p)) = Enc<TP>::go(phin, 0.f, 1.f);
       const R mv[10] = {P, a.jx, a.jy, a.jz, q_xx, q_yy, q_zz, q_xy, q_xz, q_yz};
-      uint32_t off = ucol;
 #pragma unroll
-      for (int k = 0; k < 10; ++k) {
-        base[off] = Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]);
-        off += uplane;
-      }
+      for (int k = 0; k < 10; ++k)
+        *(gptr<TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)) = Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]);
     };
 
     for (int p = p_first; p <= p_last; ++p) {
@@ -493,9 +552,9 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
             fo[1] = f0;
             fo[2] = fp;
           } else {
-            sh.f[fslot(cx, cy, -1) * NT + tid] = fm;
-            sh.f[fslot(cx, cy, 0) * NT + tid] = f0;
-            sh.f[fslot(cx, cy, 1) * NT + tid] = fp;
+            sh.f[fslot(cx, cy, -1) * NT + sp] = fm;
+            sh.f[fslot(cx, cy, 0) * NT + sp] = f0;
+            sh.f[fslot(cx, cy, 1) * NT + sp] = fp;
           }
         }
       }
@@ -509,14 +568,14 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         const R Gfx = pu * ux + sharp * gx;
         const R Gfy = pu * uy + sharp * gy;
         const R Gfz = pu * uz + sharp * gz;
-        sh.g[0 * NT + tid] = Gfx;
-        sh.g[1 * NT + tid] = Gfy;
-        sh.g[2 * NT + tid] = Gfz;
+        sh.g[0 * NT + sp] = Gfx;
+        sh.g[1 * NT + sp] = Gfy;
+        sh.g[2 * NT + sp] = Gfz;
         if (wz && (p == 0 || p == nz - 1)) {
           // ghost plane beyond the z wall: velocity reversed, n_z reversed
-          sh.gg[0 * NT + tid] = -pu * ux + sharp * gx;
-          sh.gg[1 * NT + tid] = -pu * uy + sharp * gy;
-          sh.gg[2 * NT + tid] = -pu * uz - sharp * gz;
+          sh.gg[0 * NT + sp] = -pu * ux + sharp * gx;
+          sh.gg[1 * NT + sp] = -pu * uy + sharp * gy;
+          sh.gg[2 * NT + sp] = -pu * uz - sharp * gz;
         }
       }
       const R adv_own = literal ? (ux * gmx + uy * gmy + uz * gz) : R(0);
@@ -525,7 +584,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       // stream out of them are replaced by bounce-back at the wall node
       if (wall_tile && (gcx || gcy)) {
 #pragma unroll
-        for (int k = 0; k < 24; ++k) sh.f[k * NT + tid] = R(0);
+        for (int k = 0; k < 24; ++k) sh.f[k * NT + sp] = R(0);
       }
       __syncthreads();
 
@@ -542,7 +601,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
           for (int k = 0; k < 9; ++k) {
             const int cx = k % 3 - 1, cy = k / 3 - 1;
             if (k == 4) v[k] = fo[czi];
-            else v[k] = sh.f[fslot(cx, cy, czi - 1) * NT + tid - cy * BX - cx];
+            else v[k] = sh.f[fslot(cx, cy, czi - 1) * NT + sp - cy * BX - cx];
           }
           if (czi == 0) accum_group<R, -1>(v, accM);
           else if (czi == 1) accum_group<R, 0>(v, acc0);
@@ -566,7 +625,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
               const bool behind = zb || (lw & m) != 0u;
               R own;
               if (k == 4) own = fo[2 - czi];
-              else own = sh.f[fslot(-cx, -cy, -cz) * NT + tid];
+              else own = sh.f[fslot(-cx, -cy, -cz) * NT + sp];
               v[k] = behind ? own : R(0);
             }
             if (czi == 0) accum_group<R, -1>(v, acc0);
@@ -576,7 +635,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         }
         // divergence of the phase-field flux (forward neighbours x + c)
         {
-          auto G = [&](int comp, int cx, int cy) { return sh.g[comp * NT + tid + cy * BX + cx]; };
+          auto G = [&](int comp, int cx, int cy) { return sh.g[comp * NT + sp + cy * BX + cx]; };
           R hx = R(0), hy = R(0), hz = R(0);
 #pragma unroll
           for (int cy = -1; cy <= 1; ++cy) {
@@ -601,7 +660,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
           d0 += R(4) * hxy;
           dP = hxy - hz;
           if (zb_lo || zb_hi) {
-            auto GG = [&](int comp, int cx, int cy) { return sh.gg[comp * NT + tid + cy * BX + cx]; };
+            auto GG = [&](int comp, int cx, int cy) { return sh.gg[comp * NT + sp + cy * BX + cx]; };
             R gx2 = R(0), gy2 = R(0), gz2 = R(0);
 #pragma unroll
             for (int cy = -1; cy <= 1; ++cy) {
@@ -909,7 +968,7 @@ hipError_t launch_fused_t(int precision, const BoxDesc* d_boxes, const Item* d_i
 
 bool fused_config_supported(int precision, int bx, int by) {
   if (bx == 66 && by == 8) return precision != kF64;  // FP64 needs > 168 VGPRs: would spill
-  return (bx == 32 && by == 8) || (bx == 34 && by == 8) || (bx == 34 && by == 15);
+  return (bx == 32 && by == 8) || (bx == 34 && by == 8) || (bx == 34 && by == 15) || (bx == 18 && by == 14);
 }
 
 size_t phi_bytes(int precision, int64_t n) { return static_cast<size_t>(n) * (precision == kF64 ? 8 : 4); }
@@ -923,6 +982,7 @@ int fused_blocks_per_cu(int precision, int bx, int by) {
   if (bx == 32 && by == 8) return fused_blocks_per_cu_t<32, 8>(precision);
   if (bx == 34 && by == 8) return fused_blocks_per_cu_t<34, 8>(precision);
   if (bx == 34 && by == 15) return fused_blocks_per_cu_t<34, 15>(precision);
+  if (bx == 18 && by == 14) return fused_blocks_per_cu_t<18, 14>(precision);
   if (precision == kF32) return fused_blocks_per_cu_t<66, 8, PF32>();
   if (precision == kF16) return fused_blocks_per_cu_t<66, 8, PF16>();
   return fused_blocks_per_cu_t<66, 8, PBF16>();
@@ -936,6 +996,7 @@ hipError_t launch_fused(int precision, int bx, int by, const BoxDesc* d_boxes, c
   if (bx == 32 && by == 8) return launch_fused_t<32, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
   if (bx == 34 && by == 8) return launch_fused_t<34, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
   if (bx == 34 && by == 15) return launch_fused_t<34, 15>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 18 && by == 14) return launch_fused_t<18, 14>(precision, d_boxes, d_items, n_items, grid, parity, stream);
   if (bx == 66 && by == 8) {
     if (precision == kF32) return launch_fused_t<66, 8, PF32>(d_boxes, d_items, n_items, grid, parity, stream);
     if (precision == kF16) return launch_fused_t<66, 8, PF16>(d_boxes, d_items, n_items, grid, parity, stream);

@@ -591,7 +591,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
   if (steps < 1) return fail(c, LBM_ERR_ARG, "lbm_autotune: steps must be >= 1");
   for (size_t i = 0; i < c->boxes.size(); ++i)
     if (!c->boxes[i].initialized) return fail(c, LBM_ERR_STATE, "lbm_autotune: box %zu not initialised", i);
-  const int shapes[4][2] = {{32, 8}, {34, 8}, {34, 15}, {66, 8}};
+  const int shapes[5][2] = {{32, 8}, {34, 8}, {34, 15}, {18, 14}, {66, 8}};
   int maxz = 1;
   for (auto& b : c->boxes) maxz = std::max(maxz, b.prm.nz);
   std::vector<int> fixed_zcs;

@@ -28,7 +28,7 @@ def _prob(dims, bc, **kw):
     return Problem(*dims, bc=bc, **base)
 
 
-TUNINGS = [(32, 8, 64, 0), (34, 8, 7, 0), (34, 15, 16, 0), (32, 8, 5, 3), (34, 8, 1, 0)]
+TUNINGS = [(32, 8, 64, 0), (34, 8, 7, 0), (34, 15, 16, 0), (32, 8, 5, 3), (34, 8, 1, 0), (18, 14, 4, 0)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -37,7 +37,8 @@ def test_tile_shapes_give_bitwise_identical_results(precision):
     prob = _prob((45, 23, 19), (W_, P_, W_))
     state = smooth_random_state(prob, 3)
     outs = []
-    for t in TUNINGS:
+    tunings = TUNINGS + ([(66, 8, 9, 0)] if precision != "fp64" else [])
+    for t in tunings:
         _log("tuning %s %s" % (t, precision))
         with lbm.Context(prob, precision) as ctx:
             ctx.set_tuning(*t)
