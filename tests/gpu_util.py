@@ -145,7 +145,9 @@ def sample_points(prob, rng, n_random=24, extra=()):
         pts.add((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
     for c in extra:
         pts.add(tuple(int(v) for v in c))
-    return sorted(pts)
+    # the fixed probes assume at least 3 nodes per axis: clamp them into the box
+    clamp = lambda v, n: max(0, min(v, n - 1))
+    return sorted({(clamp(x, nx), clamp(y, ny), clamp(z, nz)) for x, y, z in pts})
 
 
 def field_tolerance(precision, ref):

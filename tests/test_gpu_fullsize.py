@@ -18,6 +18,29 @@ def _log(msg):
     sys.stdout.flush()
 
 
+def _reference(case, precision, pts):
+    """Per-node oracle step at pts from the stored (quantised) initial state."""
+    prob = case.problem
+    q = lambda a, k: None if a is None else quantize(a, precision, k)
+    u = case.u
+    st = LazyState(q(case.phi, 0), None if case.pstar is None else q(case.pstar, 1),
+                   tuple(None if u is None else q(u[a], 2 + a) for a in range(3)))
+    ref = PW.step_points(st, prob, pts)
+    return np.concatenate([ref["phi"][None], ref["P"][None], ref["J"].T,
+                           np.stack([ref["Q"][:, 0, 0], ref["Q"][:, 1, 1], ref["Q"][:, 2, 2],
+                                     ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
+
+
+def _compare(got, refa, precision):
+    tols = field_tolerance(precision, refa)
+    for k, name in enumerate(FIELDS):
+        scale = np.abs(refa[k]).max()
+        tol = tols[k]
+        err = np.abs(got[k] - refa[k])
+        _log("  %-4s max err %.3e scale %.3e worst/tol %.3f" % (name, err.max(), scale, (err / tol).max()))
+        assert (err <= tol).all(), name
+
+
 def _check(case, precision, tune=True, extra=()):
     prob = case.problem
     rng = np.random.default_rng(123)
@@ -31,21 +54,7 @@ def _check(case, precision, tune=True, extra=()):
         _log("tuning %s" % ctx.tuning())
         ctx.step(1)
         got = ctx.state_at(0, pts)
-    q = lambda a, k: None if a is None else quantize(a, precision, k)
-    u = case.u
-    st = LazyState(q(case.phi, 0), None if case.pstar is None else q(case.pstar, 1),
-                   tuple(None if u is None else q(u[a], 2 + a) for a in range(3)))
-    ref = PW.step_points(st, prob, pts)
-    refa = np.concatenate([ref["phi"][None], ref["P"][None], ref["J"].T,
-                           np.stack([ref["Q"][:, 0, 0], ref["Q"][:, 1, 1], ref["Q"][:, 2, 2],
-                                     ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
-    tols = field_tolerance(precision, refa)
-    for k, name in enumerate(FIELDS):
-        scale = np.abs(refa[k]).max()
-        tol = tols[k]
-        err = np.abs(got[k] - refa[k])
-        _log("  %-4s max err %.3e scale %.3e worst/tol %.3f" % (name, err.max(), scale, (err / tol).max()))
-        assert (err <= tol).all(), name
+    _compare(got, _reference(case, precision, pts), precision)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -60,3 +69,44 @@ def test_drop_into_pool_512_one_step(precision):
     case = workloads.drop_into_pool()
     extra = [(256, 256, 127), (256, 256, 128), (256, 256, 220), (256, 256, 300), (0, 0, 511), (511, 511, 0)]
     _check(case, precision, tune=True, extra=extra)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16_os"])
+def test_droplet_collision_256_one_step(precision):
+    case = workloads.droplet_collision()
+    extra = [(120, 128, 128), (136, 128, 128), (128, 128, 128), (96, 128, 128), (160, 128, 128)]
+    _check(case, precision, extra=extra)
+
+
+def test_ensemble_64_boxes_one_launch_one_step():
+    """All 64 boxes of uneven sizes in one launch per step, in the tile shape
+    and z-chunk the FP32 benchmark autotunes to, each box checked at sampled
+    nodes against the per-node oracle.  The check runs in FP64 (1e-12 of each
+    box's population scale): the droplets start at rest, so one step moves P
+    and J by amounts far below FP32 rounding of the forces; the FP32 batched
+    launch is checked bitwise against separate single-box launches
+    elsewhere."""
+    cases = workloads.ensemble()
+    with lbm.Context([c.problem for c in cases], "fp32") as ctx:
+        for i, c in enumerate(cases):
+            ctx.init_case(i, c)
+        ctx.autotune(2)
+        t = ctx.tuning()
+    _log("ensemble fp32 tuning %s" % t)
+    with lbm.Context([c.problem for c in cases], "fp64") as ctx:
+        bx = 34 if (t["block_x"], t["block_y"]) == (66, 8) else t["block_x"]  # 66 x 8 has no FP64 form
+        ctx.set_tuning(bx, t["block_y"], t["z_chunk"], t["persistent"])
+        for i, c in enumerate(cases):
+            ctx.init_case(i, c)
+        ctx.step(1)
+        rng = np.random.default_rng(77)
+        for i, c in enumerate(cases):
+            pts = sample_points(c.problem, rng, n_random=4)
+            got = ctx.state_at(i, pts)
+            refa = _reference(c, "fp64", pts)
+            s_mom = max(np.abs(refa[1]).max(), np.abs(refa[2:5]).max())
+            for k, name in enumerate(FIELDS):
+                scale = np.abs(refa[k]).max() if k == 0 else max(np.abs(refa[k]).max(), s_mom)
+                err = np.abs(got[k] - refa[k]).max()
+                assert err <= 1e-12 * scale, (i, name, err, scale)
+        _log("64 boxes checked")

@@ -68,3 +68,37 @@ def test_static_droplet_100_steps_fp64():
         l2 = np.linalg.norm(a - b) / np.linalg.norm(b)
         mx = np.abs(a - b).max() / np.abs(b).max()
         assert l2 <= 1e-10 and mx <= 1e-10, (name, l2, mx)
+
+
+def test_largest_plane_fp64():
+    """nx * ny = 2^28, the largest plane the library accepts: per-lane byte
+    offsets inside one FP64 plane reach 2^31.  One step from a smooth phase
+    field, checked at sampled nodes (edges of the plane included) against the
+    per-node oracle."""
+    from oracle import pointwise as PW
+    from tests.gpu_util import LazyState, sample_points
+
+    n = 1 << 14
+    prob = Problem(n, n, 1, bc=(P_, P_, P_), rho_l=1.0, rho_g=0.01, nu_l=0.02, nu_g=0.1,
+                   sigma=0.01, gravity=(1e-6, 0.0, 2e-6))
+    k = 2 * np.pi * 64 / n
+    x = np.arange(n, dtype=np.float64)
+    phi = (0.5 + 0.45 * np.sin(k * x)[None, :] * np.cos(k * x)[:, None])[None]
+    pts = sample_points(prob, np.random.default_rng(9), n_random=16,
+                        extra=[(n - 1, n - 1, 0), (n - 1, 0, 0), (0, n - 1, 0), (n // 2, n - 1, 0)])
+    _log("largest plane %dx%dx1 fp64, %d points" % (n, n, len(pts)))
+    with lbm.Context(prob, "fp64") as ctx:
+        ctx.init_phase(0, phi, None, None)
+        ctx.step(1)
+        got = ctx.state_at(0, pts)
+    ref = PW.step_points(LazyState(phi), prob, pts)
+    refa = np.concatenate([ref["phi"][None], ref["P"][None], ref["J"].T,
+                           np.stack([ref["Q"][:, 0, 0], ref["Q"][:, 1, 1], ref["Q"][:, 2, 2],
+                                     ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
+    # each moment is a signed sum of populations of size max(|P|, |J|): FP64
+    # agreement is judged on that scale (some Q components are far smaller)
+    s_mom = max(np.abs(refa[1]).max(), np.abs(refa[2:5]).max())
+    for kf in range(11):
+        scale = np.abs(refa[kf]).max() if kf == 0 else max(np.abs(refa[kf]).max(), s_mom)
+        err = np.abs(got[kf] - refa[kf]).max()
+        assert err <= 1e-12 * scale, (kf, err, scale)
