@@ -55,6 +55,13 @@ class PointOracle:
         zs = self._map(2, z)[0]
         return self.st.phi[zs, ys, xs]
 
+    def J_at(self, x, y, z):
+        """J at a node that may be a ghost: minus the mirrored value per crossed wall (R11)."""
+        xs, mx = self._map(0, x)
+        ys, my = self._map(1, y)
+        zs, mz = self._map(2, z)
+        return self.st.J[:, zs, ys, xs] * (-1.0) ** (mx + my + mz)
+
     # -- node quantities at an in-domain node ---------------------------------
     def node(self, x, y, z):
         key = (x, y, z)
@@ -73,11 +80,22 @@ class PointOracle:
         grho = scheme.density_gradient(gphi, prob)
         P = st.P[z, y, x]
         J = st.J[:, z, y, x].copy()
-        Qt = st.Q[:, :, z, y, x].copy()
-        F = scheme.total_force(np.float64(phi), gphi, np.float64(lap), grho,
-                               np.float64(P), Qt, prob)
         om = scheme.relaxation(scheme.viscosity(phi, prob))
-        fpost, u, A, a = scheme.collide(np.float64(P), J, Qt, F, rho_c, om)
+        if prob.gradient_closure:
+            # a2 from the isotropic gradient of J, neighbours by index (G1-G3)
+            gJ = np.zeros((3, 3))
+            for i in range(NQ):
+                cx, cy, cz = (int(v) for v in C[i])
+                gJ += (W[i] / CS2) * np.outer(self.J_at(x + cx, y + cy, z + cz), C[i])
+            A = -(CS2 / om) * (gJ + gJ.T)
+            F = scheme.total_force(np.float64(phi), gphi, np.float64(lap), grho,
+                                   np.float64(P), A, prob)
+            fpost, u, A, a = scheme.collide_closed(np.float64(P), J, A, F, rho_c, om)
+        else:
+            Qt = st.Q[:, :, z, y, x].copy()
+            F = scheme.total_force(np.float64(phi), gphi, np.float64(lap), grho,
+                                   np.float64(P), Qt, prob)
+            fpost, u, A, a = scheme.collide(np.float64(P), J, Qt, F, rho_c, om)
         mag = np.sqrt(np.sum(gphi ** 2))
         res = dict(phi=phi, grad_phi=gphi, lap=lap, u=u, fpost=fpost,
                    n=gphi / (mag + scheme.EPS_NORMAL))
@@ -115,6 +133,8 @@ class PointOracle:
         J = C.T.astype(np.float64) @ f
         Pi = np.einsum("i,ia,ib->ab", f, C.astype(np.float64), C.astype(np.float64))
         Qn = Pi - CS2 * P * np.eye(3) - np.outer(J, J)
+        if prob.gradient_closure:
+            Qn = np.zeros((3, 3))  # not part of the state (G4)
 
         kac = 4.0 * prob.mobility / prob.width
         div_adv = 0.0

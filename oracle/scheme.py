@@ -67,6 +67,22 @@ the design notes of the repository):
       Peclet number u/M > 2 over- and undershoots slightly; unclamped, an
       undershoot below -rho_g/(rho_l - rho_g) makes rho <= 0 at density ratio
       1000 and an overshoot can make nu < 0.
+
+Gradient-closure variant (Problem.gradient_closure; the alternative a2 of
+Eq. noneqts, stated there as a velocity-gradient expression):
+  G1  a2_ab = -(cs^2/omega) (d_a u_b + d_b u_a): the Chapman-Enskog value of
+      the non-equilibrium second moment for populations normalised like these
+      (sum f = p*, sum f c = u).  The printed prefactor -1/(omega cs^2) acting
+      on grad(rho u) is read as this density-normalised form.
+  G2  The gradient is taken of the stored first moment J (the isotropic
+      gradient of R6, ghosts by R11: minus the mirrored value), not of
+      u = J + a/2: a at a neighbour needs that neighbour's viscous force,
+      which needs its own velocity gradient, so J keeps the step explicit;
+      the two differ by grad(a)/2, first order in the force.
+  G3  The viscous correction (Eq. visc_corr) uses the same a2 in place of the
+      moment-based tensor.
+  G4  The state is phi, P, J (5 fields); Q is neither stored nor used and is
+      kept zero in State.
 """
 from __future__ import annotations
 
@@ -291,6 +307,29 @@ def second_moment(f):
     return np.einsum("iab,i...->ab...", H2_ALL, f)
 
 
+def velocity_gradient(J, prob):
+    """grad J as (a, b, ...) = d_b J_a: the isotropic gradient (R6) of each
+    component, ghost values minus the mirrored value at walls (R11; G2)."""
+    return np.stack([grad(pad(J[a], prob, 1, odd=(True, True, True)), 1) for a in range(3)])
+
+
+def gradient_closure_tensor(grad_J, omega):
+    """a2 = -(cs^2/omega) (d_a J_b + d_b J_a)  (Eq. noneqts, velocity-gradient form; G1, G2)."""
+    return -(CS2 / omega) * (grad_J + np.swapaxes(grad_J, 0, 1))
+
+
+def collide_closed(P, J, A, F, rho, omega):
+    """Post-collision populations with the regularisation tensor given:
+    u = J + a/2, f_post = feq(P, u) + (1 - omega) f_neq(A, u) + S/2
+    (Eqs. moments1, LBexp, noneqts, guoforce; R3, R4)."""
+    a = F / rho
+    u = J + 0.5 * a
+    feq = f_eq(P, u)
+    S = guo_source(u, a)
+    fpost = feq + (1.0 - omega) * f_neq(A, u) + 0.5 * S
+    return fpost, u, A, a
+
+
 def collide(P, J, Q, F, rho, omega):
     """Moments -> velocity -> pre-regularisation -> post-collision populations.
 
@@ -323,9 +362,14 @@ def node_fields(st, prob):
     grho = density_gradient(gphi, prob)
     nu = viscosity(st.phi, prob)
     om = relaxation(nu)
-    F = total_force(st.phi, gphi, lphi, grho, st.P, st.Q, prob)
+    A = None
+    if prob.gradient_closure:
+        A = gradient_closure_tensor(velocity_gradient(st.J, prob), om)
+        F = total_force(st.phi, gphi, lphi, grho, st.P, A, prob)   # G3
+    else:
+        F = total_force(st.phi, gphi, lphi, grho, st.P, st.Q, prob)
     return dict(phip=phip, grad_phi=gphi, lap_phi=lphi, rho=rho, grad_rho=grho,
-                nu=nu, omega=om, F=F)
+                nu=nu, omega=om, F=F, A=A)
 
 
 def stream_push(fpost, prob):
@@ -386,9 +430,14 @@ def phase_update(st, nf, u, prob):
 def step(st, prob):
     """One full time step, phases 1-4 of Sec. II.D."""
     nf = node_fields(st, prob)
-    fpost, u, _, _ = collide(st.P, st.J, st.Q, nf["F"], nf["rho"], nf["omega"])
+    if prob.gradient_closure:
+        fpost, u, _, _ = collide_closed(st.P, st.J, nf["A"], nf["F"], nf["rho"], nf["omega"])
+    else:
+        fpost, u, _, _ = collide(st.P, st.J, st.Q, nf["F"], nf["rho"], nf["omega"])
     f = stream_push(fpost, prob)
     P, J, Q = moments(f)
+    if prob.gradient_closure:
+        Q = np.zeros_like(Q)  # G4
     phi = phase_update(st, nf, u, prob)
     return State(phi, P, J, Q)
 

@@ -43,6 +43,7 @@ class Problem:
     gravity: tuple = (0.0, 0.0, 0.0)
     rho_ref: float = 0.0      # body force density is (rho - rho_ref) * gravity
     literal_advection: bool = False  # u.grad(phi) instead of div(phi u)
+    gradient_closure: bool = False   # a2 from the velocity gradient; state phi, P, J only
 
     @property
     def shape(self):
