@@ -294,9 +294,13 @@ def summarize_counters(args):
     data = json.load(open(path)) if os.path.exists(path) else {}
     cases, _ = make_cases(args.config)
     nodes = sum(c.problem.n_nodes for c in cases)
-    bpl = {"fp64": 176, "fp32": 88, "fp16_os": 48, "bf16_os": 48}[args.precision.split(",")[0]]
+    prec = args.precision.split(",")[0]
+    gc = args.closure == "gradient"
+    # algorithmic bytes per update: phi + moment fields, read and written
+    bpl = 2 * ({"fp64": 8, "fp32": 4}.get(prec, 4) + (4 if gc else 10) * {"fp64": 8, "fp32": 4}.get(prec, 2))
     tuning = [int(v) for v in args.tuning.split(",")] if args.tuning else None
-    data["%s/%s" % (args.config, args.precision.split(",")[0])] = {
+    key = "%s%s/%s" % (args.config, "/gc" if gc else "", prec)
+    data[key] = {
         "kernel_hash": kernel_hash(), "tuning": tuning,
         "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
         "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_fetch, "write_scale": f_write,
@@ -304,7 +308,7 @@ def summarize_counters(args):
         "bytes_per_update_algorithmic": bpl}
     with open(path, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
-    print(json.dumps(data["%s/%s" % (args.config, args.precision.split(",")[0])]))
+    print(json.dumps(data[key]))
 
 
 def main():
@@ -329,6 +333,9 @@ def main():
     ap.add_argument("--copy-fetch-csv")
     ap.add_argument("--copy-write-csv")
     ap.add_argument("--copy-kernel", default="elementwise")
+    ap.add_argument("--closure", default="moment", choices=["moment", "gradient"],
+                    help="a2 from the stored second moment (the paper's algorithm) or from the "
+                         "velocity gradient (5-field state)")
     ap.add_argument("--tuning", default=None, metavar="BX,BY,ZCHUNK,PERSISTENT",
                     help="fixed launch configuration instead of autotuning")
     args = ap.parse_args()
@@ -353,6 +360,10 @@ def main():
     precisions = (args.precision or defaults[args.config]).split(",")
     log("bench: building cases for %s" % args.config)
     cases, desc = make_cases(args.config)
+    if args.closure == "gradient":
+        for c in cases:
+            c.problem.gradient_closure = True
+        desc += ", gradient closure (state phi, P, J)"
     modes = {}
     for prec in precisions:
         log("bench: %s %s: %d warmup + %d timed steps" % (args.config, prec, args.warmup, args.steps))
@@ -370,7 +381,7 @@ def main():
         log("bench: C4 unbatched: %.0f MLUPS" % modes[prec + "_unbatched"]["mlups"])
     head = precisions[0]
     m = modes[head]
-    traffic = measured_traffic(args.config, head, m["tuning"])
+    traffic = measured_traffic(args.config + ("/gc" if args.closure == "gradient" else ""), head, m["tuning"])
     copy_gbs = copy_bandwidth()
     log("bench: device copy %.0f GB/s" % copy_gbs)
     roof = {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -395,7 +406,8 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[head],
         "data": "synthetic (seeded initial droplet/bubble fields)",
-        "config": {"workload": desc, "config": args.config, "nodes": m["nodes"], "precision": head,
+        "config": {"workload": desc, "config": args.config, "closure": args.closure, "nodes": m["nodes"],
+                   "precision": head,
                    "tuning": m["tuning"], "steps_per_launch": 1},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -77,7 +77,15 @@ typedef enum {
 enum {
   /* Advect phi with u.grad(phi) as printed in the FTCS update of Sec. II.D
    * instead of the conservative flux form div(phi u). */
-  LBM_LITERAL_ADVECTION = 1
+  LBM_LITERAL_ADVECTION = 1,
+  /* Gradient closure: rebuild the non-equilibrium second moment from the
+   * velocity gradient, a2 = -(cs^2/omega)(grad J + grad J^T) (the
+   * velocity-gradient a2 given with Eq. noneqts; J = sum f c, isotropic
+   * gradient of Sec. II.C), also in the viscous correction (Eq. visc_corr).
+   * The state is then phi, P, J only: 5 stored fields per node instead of
+   * 11, and the Q fields of lbm_get_state read 0 (lbm_set_state ignores
+   * them).  All boxes of a context must agree on this flag. */
+  LBM_GRADIENT_CLOSURE = 2
 };
 
 /* One box.  phi = 1 is the liquid (subscript l), phi = 0 the gas (g). */
@@ -86,7 +94,7 @@ typedef struct {
   int32_t lattice;        /* lbm_lattice */
   int32_t bc[3];          /* lbm_bc per axis x, y, z */
   int32_t precision;      /* lbm_precision; identical for all boxes of a context */
-  int32_t flags;          /* LBM_LITERAL_ADVECTION or 0 */
+  int32_t flags;          /* LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE, or 0 */
   double rho_l, rho_g;    /* phase densities, > 0 (Sec. II.C) */
   double nu_l, nu_g;      /* kinematic viscosities, > 0; omega = 1/(3 nu + 1/2) */
   double sigma;           /* surface tension, >= 0 (Sec. II.C: beta = 12 sigma/W, kappa = 3 sigma W/2) */
@@ -126,7 +134,7 @@ typedef struct {
 
 /* Tile / launch configuration of the fused step (chosen by lbm_autotune). */
 typedef struct {
-  int32_t block_x, block_y; /* workgroup columns; supported pairs: (32,8) (34,8) (34,15) (18,14), and (66,8) except in FP64 */
+  int32_t block_x, block_y; /* workgroup columns; supported pairs: (32,8) (34,8) (34,15); with the moment closure also (18,14), and (66,8) except in FP64 */
   int32_t z_chunk;          /* planes marched by one workgroup, >= 1 */
   int32_t persistent;       /* 0: one workgroup per tile; n > 0: n workgroups loop over tiles */
 } lbm_tuning;
@@ -135,7 +143,8 @@ typedef struct {
  * (one launch per step covers every box).  All parameters are validated before
  * any device call.  The state is undefined until lbm_init_phase or
  * lbm_set_state has been called for every box.  On success *out owns all
- * device memory of the state (2 x 11 fields per box, ping-pong). */
+ * device memory of the state (2 x 11 fields per box, ping-pong; 2 x 5 with
+ * LBM_GRADIENT_CLOSURE). */
 lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device* dev,
                       lbm_ctx** out);
 

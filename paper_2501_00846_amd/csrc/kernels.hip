@@ -226,11 +226,13 @@ __device__ __forceinline__ void lane_position(int tid, int& tx, int& ty) {
   ty = h + 1;
 }
 
-template <int BX, int BY, class PR>
+template <int BX, int BY, class PR, bool GC>
 struct FusedShared {
   using R = typename PR::R;
   static constexpr int NT = BX * BY;
-  R phi[(BY + 2) * (BX + 2)];
+  static constexpr int NP = (BY + 2) * (BX + 2);
+  R phi[NP];
+  R jp[GC ? 3 * NP : 1];  // gradient closure: J of the staged plane, halo 2
   R f[24 * NT];
   R g[3 * NT];
   R gg[3 * NT];
@@ -245,7 +247,14 @@ struct FusedShared {
 template <class PR> struct WavesPerEU { static constexpr int v = 4; };
 template <> struct WavesPerEU<PF64> { static constexpr int v = 2; };
 
-template <int BX, int BY, class PR>
+// GC selects the gradient-closure variant: the state holds phi, P and J only
+// (4 moment fields per plane instead of 10) and a2 is rebuilt from the
+// isotropic gradient of J, a2 = -(cs^2/omega)(grad J + grad J^T) (the
+// velocity-gradient a2 given with Eq. noneqts), which also feeds the viscous
+// correction.  J is staged like phi (two-column halo) so that the halo-ring
+// nodes get their gradient too; its ghost values are minus the mirrored ones
+// (sign (-1)^(walls crossed)), the ghost rule of the velocity.
+template <int BX, int BY, class PR, bool GC>
 __global__ void __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(WavesPerEU<PR>::v)))
 fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, int n_items,
            int parity) {
@@ -255,7 +264,8 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
   constexpr int NT = BX * BY;
   constexpr int PX = BX + 2;
   constexpr int PY = BY + 2;
-  __shared__ FusedShared<BX, BY, PR> sh;
+  constexpr int NM = GC ? 4 : 10;  // moment fields per plane
+  __shared__ FusedShared<BX, BY, PR, GC> sh;
 
   const int tid = threadIdx.x;
   int tx, ty;
@@ -319,6 +329,20 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       phcol[j] = static_cast<uint32_t>(map_axis(item.y0 - 2 + jj, ny, wy) * nx + map_axis(item.x0 - 2 + i, nx, wx)) *
                  static_cast<uint32_t>(sizeof(TP));
     }
+    // gradient closure: bit j set when halo element j lies across an odd
+    // number of x/y walls (its J enters with the opposite sign)
+    uint32_t jflip = 0;
+    if constexpr (GC) {
+#pragma unroll
+      for (int j = 0; j < NPH; ++j) {
+        const int e = tid + j * NT;
+        const int i = e % PX, jj = e / PX;
+        int cx, cy;
+        (void)map_axis(item.x0 - 2 + i, nx, wx, cx);
+        (void)map_axis(item.y0 - 2 + jj, ny, wy, cy);
+        jflip |= static_cast<uint32_t>(cx ^ cy) << j;
+      }
+    }
     // phi of one plane at this thread's halo elements: loaded one plane ahead
     // into registers, stored to LDS when the plane is needed.  Addresses are a
     // uniform plane base plus a 32-bit per-lane byte offset (a plane holds at
@@ -358,27 +382,85 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       F[2] = sx[2] - sx[0];
     };
 
+    // gradient closure: J (fields 1-3) at the same halo elements as phi
+    constexpr int NP = PX * PY;
+    auto load_J = [&](int q, R (*v)[NPH]) {
+      const gptr<const char> base = (gptr<const char>)s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * NM * plane_bm;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const gptr<const char> src = sbase(base + (1 + a) * plane_bm);
+#pragma unroll
+        for (int j = 0; j < NPH; ++j) {
+          const uint32_t off = phcol[j] / static_cast<uint32_t>(sizeof(TP)) * static_cast<uint32_t>(sizeof(TM));
+          v[a][j] = dec<R>(*(gptr<const TM>)(src + lane_off(off)), b.enc_off[1 + a], b.enc_inv[1 + a]);
+        }
+      }
+    };
+    // plane q lies beyond a z wall: every element of it is a ghost across that wall
+    auto store_J = [&](R (*v)[NPH], int q) {
+      const bool zflip = wz && (q < 0 || q >= nz);
+#pragma unroll
+      for (int j = 0; j < NPH; ++j) {
+        const int e = tid + j * NT;
+        if (j < NPH - 1 || e < NP) {
+          const bool neg = (((jflip >> j) & 1u) != 0u) != zflip;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) sh.jp[a * NP + e] = neg ? -v[a][j] : v[a][j];
+        }
+      }
+    };
+    // F[a] = (s_x s_y J_a, s_y d_x J_a, s_x d_y J_a)
+    auto filter_J = [&](R (*F)[3]) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        R dx[3], sx[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const R* row = &sh.jp[a * NP + (ty + r) * PX + tx];
+          const R l = row[0], c = row[1], h = row[2];
+          dx[r] = h - l;
+          sx[r] = l + R(4) * c + h;
+        }
+        F[a][0] = sx[0] + R(4) * sx[1] + sx[2];
+        F[a][1] = dx[0] + R(4) * dx[1] + dx[2];
+        F[a][2] = sx[2] - sx[0];
+      }
+    };
+
     R Fm[4], F0[4], Fp[4];
+    R JFm[GC ? 3 : 1][3], JF0[GC ? 3 : 1][3], JFp[GC ? 3 : 1][3];
+    R jnxt[GC ? 3 : 1][NPH];
     stage_phi(p_first - 1);
+    if constexpr (GC) {
+      load_J(p_first - 1, jnxt);
+      store_J(jnxt, p_first - 1);
+    }
     __syncthreads();
     filter_phi(Fm);
+    if constexpr (GC) filter_J(JFm);
     __syncthreads();
     stage_phi(p_first);
+    if constexpr (GC) {
+      load_J(p_first, jnxt);
+      store_J(jnxt, p_first);
+    }
     __syncthreads();
     filter_phi(F0);
+    if constexpr (GC) filter_J(JF0);
     __syncthreads();
 
     // moments of the own column, prefetched one plane ahead
-    R nxt[10];
+    R nxt[NM];
     auto load_moments = [&](int q, R* m) {
-      const gptr<const char> base = (gptr<const char>)s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * 10 * plane_bm;
+      const gptr<const char> base = (gptr<const char>)s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * NM * plane_bm;
 #pragma unroll
-      for (int k = 0; k < 10; ++k)
+      for (int k = 0; k < NM; ++k)
         m[k] = dec<R>(*(gptr<const TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), b.enc_off[k], b.enc_inv[k]);
     };
     load_moments(p_first, nxt);
     R phinxt[NPH];
     load_phi(p_first + 1, phinxt);
+    if constexpr (GC) load_J(p_first + 1, jnxt);
 
     // Prefetched registers are consumed here, before this plane's global
     // stores are issued: loads and stores retire through one in-order vector
@@ -387,9 +469,15 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     // every store.
     auto settle_prefetch = [&]() {
 #pragma unroll
-      for (int k = 0; k < 10; ++k) asm volatile("" ::"v"(nxt[k]));
+      for (int k = 0; k < NM; ++k) asm volatile("" ::"v"(nxt[k]));
 #pragma unroll
       for (int j = 0; j < NPH; ++j) asm volatile("" ::"v"(phinxt[j]));
+      if constexpr (GC) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int j = 0; j < NPH; ++j) asm volatile("" ::"v"(jnxt[a][j]));
+      }
     };
 
     // The loop header joins this path with the back edge, where the prefetched
@@ -406,7 +494,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     R phiH = R(0), lapH = R(0), advH = R(0);  // own-node phi, lap(phi), u.grad(phi) of plane p-1
 
     auto finalize = [&](int Z, const Acc<R>& a, R d, R phic, R lapc, R advc) {
-      const gptr<char> base = (gptr<char>)d_mom + static_cast<int64_t>(Z) * 10 * plane_bm;
+      const gptr<char> base = (gptr<char>)d_mom + static_cast<int64_t>(Z) * NM * plane_bm;
       const R P = a.p;
       const R q_xx = a.xx - P * R(1.0 / 3.0) - a.jx * a.jx;
       const R q_yy = a.yy - P * R(1.0 / 3.0) - a.jy * a.jy;
@@ -418,21 +506,26 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       *(gptr<TP>)(sbase((gptr<char>)d_phi_g + static_cast<int64_t>(Z) * plane_bp) + lane_off(voff_p)) = Enc<TP>::go(phin, 0.f, 1.f);
       const R mv[10] = {P, a.jx, a.jy, a.jz, q_xx, q_yy, q_zz, q_xy, q_xz, q_yz};
 #pragma unroll
-      for (int k = 0; k < 10; ++k)
+      for (int k = 0; k < NM; ++k)
         *(gptr<TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)) = Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]);
     };
 
     for (int p = p_first; p <= p_last; ++p) {
-      R cur[10];
+      R cur[NM];
 #pragma unroll
-      for (int k = 0; k < 10; ++k) cur[k] = nxt[k];
+      for (int k = 0; k < NM; ++k) cur[k] = nxt[k];
       if (p < p_last) load_moments(p + 1, nxt);
 
       // (A) phi plane p+1 (prefetched) -> LDS -> filtered registers; prefetch p+2
       store_phi(phinxt);
       if (p < p_last) load_phi(p + 2, phinxt);
+      if constexpr (GC) {
+        store_J(jnxt, p + 1);
+        if (p < p_last) load_J(p + 2, jnxt);
+      }
       __syncthreads();
       filter_phi(Fp);
+      if constexpr (GC) filter_J(JFp);
 
       // (B) node quantities at (column, p)
       const R phi = F0[3];
@@ -449,7 +542,6 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 
       const R P = cur[0];
       const R Jx = cur[1], Jy = cur[2], Jz = cur[3];
-      const R Qxx = cur[4], Qyy = cur[5], Qzz = cur[6], Qxy = cur[7], Qxz = cur[8], Qyz = cur[9];
 
       // density, viscosity and relaxation interpolation in FP64 (Sec. II.C),
       // evaluated at phi clamped to the model's range [0, 1]
@@ -465,12 +557,51 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R irho = static_cast<R>(inv_rho);
       const R cvis = static_cast<R>(-3.0 * nu * om_d * b.drho * inv_rho);
 
+      // The tensor the viscous correction contracts: the stored Q, or for the
+      // gradient closure a2 itself, -(cs^2/omega)(d_a J_b + d_b J_a) with the
+      // isotropic gradient of J (filtered planes p-1, p, p+1).  A ghost lane
+      // (halo column beyond an x/y wall) sees J reflected with sign
+      // s = (-1)^(walls crossed); the mirror node's gradient is its own times
+      // s, and times -1 again along each crossed axis.
+      R Txx, Tyy, Tzz, Txy, Txz, Tyz;
+      if constexpr (GC) {
+        R gJ[3][3];  // gJ[a][c] = d_c J_a
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          gJ[a][0] = (JFm[a][1] + R(4) * JF0[a][1] + JFp[a][1]) * R(1.0 / 72.0);
+          gJ[a][1] = (JFm[a][2] + R(4) * JF0[a][2] + JFp[a][2]) * R(1.0 / 72.0);
+          gJ[a][2] = (JFp[a][0] - JFm[a][0]) * R(1.0 / 72.0);
+        }
+        const R sg = (gcx != gcy) ? R(-1) : R(1);
+        const R sdx = gcx ? -sg : sg, sdy = gcy ? -sg : sg;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          gJ[a][0] *= sdx;
+          gJ[a][1] *= sdy;
+          gJ[a][2] *= sg;
+        }
+        const R ca = static_cast<R>(-tau * (1.0 / 3.0));  // -cs^2 / omega
+        Txx = ca * (gJ[0][0] + gJ[0][0]);
+        Tyy = ca * (gJ[1][1] + gJ[1][1]);
+        Tzz = ca * (gJ[2][2] + gJ[2][2]);
+        Txy = ca * (gJ[0][1] + gJ[1][0]);
+        Txz = ca * (gJ[0][2] + gJ[2][0]);
+        Tyz = ca * (gJ[1][2] + gJ[2][1]);
+      } else {
+        Txx = cur[4 % NM];
+        Tyy = cur[5 % NM];
+        Tzz = cur[6 % NM];
+        Txy = cur[7 % NM];
+        Txz = cur[8 % NM];
+        Tyz = cur[9 % NM];
+      }
+
       // chemical potential and the force per unit mass a = F / rho
       const R mu = beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - kappa_mu * lap;
       const R csp = (mu - P * drho3) * irho;  // (F^s + F^p) / rho on grad(phi)
-      const R qgx = Qxx * gmx + Qxy * gmy + Qxz * gz;
-      const R qgy = Qxy * gmx + Qyy * gmy + Qyz * gz;
-      const R qgz = Qxz * gmx + Qyz * gmy + Qzz * gz;
+      const R qgx = Txx * gmx + Txy * gmy + Txz * gz;
+      const R qgy = Txy * gmx + Tyy * gmy + Tyz * gz;
+      const R qgz = Txz * gmx + Tyz * gmy + Tzz * gz;
       const R ax = csp * gmx + cvis * qgx + static_cast<R>(b.grav[0] * bfac);
       const R ay = csp * gmy + cvis * qgy + static_cast<R>(b.grav[1] * bfac);
       const R az = csp * gz + cvis * qgz + static_cast<R>(b.grav[2] * bfac);
@@ -478,13 +609,14 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R uy = Jy + R(0.5) * ay;
       const R uz = Jz + R(0.5) * az;
 
-      // a2 = Q + J J - u u + (u a + a u)/2 = Q + a a / 4
-      const R Axx = Qxx + R(0.25) * ax * ax;
-      const R Ayy = Qyy + R(0.25) * ay * ay;
-      const R Azz = Qzz + R(0.25) * az * az;
-      const R Axy = Qxy + R(0.25) * ax * ay;
-      const R Axz = Qxz + R(0.25) * ax * az;
-      const R Ayz = Qyz + R(0.25) * ay * az;
+      // a2 = Q + J J - u u + (u a + a u)/2 = Q + a a / 4 (moment closure), or
+      // the gradient closure's a2 as it is
+      const R Axx = GC ? Txx : Txx + R(0.25) * ax * ax;
+      const R Ayy = GC ? Tyy : Tyy + R(0.25) * ay * ay;
+      const R Azz = GC ? Tzz : Tzz + R(0.25) * az * az;
+      const R Axy = GC ? Txy : Txy + R(0.25) * ax * ay;
+      const R Axz = GC ? Txz : Txz + R(0.25) * ax * az;
+      const R Ayz = GC ? Tyz : Tyz + R(0.25) * ay * az;
 
       // monomial coefficients of g(c) = f_post(c) / w(c), pre-scaled by 1/216
       const R usq = ux * ux + uy * uy + uz * uz;
@@ -700,6 +832,15 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         Fm[k] = F0[k];
         F0[k] = Fp[k];
       }
+      if constexpr (GC) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            JFm[a][k] = JF0[a][k];
+            JF0[a][k] = JFp[a][k];
+          }
+      }
     }
     // top wall: the last node plane is the last output plane
     if (out_col && wz && z1 == nz) finalize(nz - 1, accM, dM, phiH, lapH, advH);
@@ -714,7 +855,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 __device__ __forceinline__ int64_t mom_index(const BoxDesc& b, int k, int64_t i) {
   const int64_t plane = static_cast<int64_t>(b.nx) * b.ny;
   const int64_t z = i / plane;
-  return (z * 10 + k) * plane + (i - z * plane);
+  return (z * b.nmom + k) * plane + (i - z * plane);
 }
 
 template <class PR>
@@ -727,7 +868,8 @@ __global__ void encode_kernel(BoxDesc b, int parity, int field, const double* __
       ((gptr<TP>)b.phi[parity])[i] = Enc<TP>::go(src[i], 0.f, 1.f);
     } else {
       const int k = field - 1;
-      ((gptr<TM>)b.mom[parity])[mom_index(b, k, i)] = Enc<TM>::go(src[i], b.enc_off[k], b.enc_scale[k]);
+      if (k < b.nmom)  // Q is not stored by the gradient closure
+        ((gptr<TM>)b.mom[parity])[mom_index(b, k, i)] = Enc<TM>::go(src[i], b.enc_off[k], b.enc_scale[k]);
     }
   }
 }
@@ -742,7 +884,8 @@ __global__ void decode_kernel(BoxDesc b, int parity, int field, double* __restri
       dst[i] = dec<double>(((gptr<const TP>)b.phi[parity])[i], 0.f, 1.f);
     } else {
       const int k = field - 1;
-      dst[i] = dec<double>(((gptr<const TM>)b.mom[parity])[mom_index(b, k, i)], b.enc_off[k], b.enc_inv[k]);
+      dst[i] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_index(b, k, i)], b.enc_off[k], b.enc_inv[k])
+                          : 0.0;
     }
   }
 }
@@ -757,7 +900,9 @@ __global__ void gather_kernel(BoxDesc b, int parity, const int64_t* __restrict__
     const int64_t i = idx[j];
     out[j] = dec<double>(((gptr<const TP>)b.phi[parity])[i], 0.f, 1.f);
     for (int k = 0; k < 10; ++k)
-      out[(k + 1) * n + j] = dec<double>(((gptr<const TM>)b.mom[parity])[mom_index(b, k, i)], b.enc_off[k], b.enc_inv[k]);
+      out[(k + 1) * n + j] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_index(b, k, i)],
+                                                      b.enc_off[k], b.enc_inv[k])
+                                        : 0.0;
   }
 }
 
@@ -776,7 +921,7 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
   const int64_t idx = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
   finite = true;
   for (int k = 0; k < 10; ++k) {
-    m[k] = dec<double>(fmom[mom_index(b, k, idx)], b.enc_off[k], b.enc_inv[k]);
+    m[k] = k < b.nmom ? dec<double>(fmom[mom_index(b, k, idx)], b.enc_off[k], b.enc_inv[k]) : 0.0;
     finite = finite && isfinite(m[k]);
   }
   phi = dec<double>(fphi[idx], 0.f, 1.f);
@@ -801,7 +946,31 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
   const double om = 1.0 / (3.0 * nu + 0.5);
   const double mu = b.beta4 * phi * (phi - 1.0) * (phi - 0.5) - b.kappa_mu * lap;
   const double P = m[0];
-  const double Q[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+  double Q[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+  if (b.flags & 2) {
+    // gradient closure: the viscous correction contracts -(cs^2/omega)(grad J + grad J^T),
+    // J ghosts minus the mirrored value per wall crossed
+    double gJ[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int cz = -1; cz <= 1; ++cz)
+      for (int cy = -1; cy <= 1; ++cy)
+        for (int cx = -1; cx <= 1; ++cx) {
+          int kx, ky, kz;
+          const int xx = map_axis(x + cx, nx, b.wall[0], kx);
+          const int yy = map_axis(y + cy, ny, b.wall[1], ky);
+          const int zz = map_axis(z + cz, nz, b.wall[2], kz);
+          const double sgn = ((kx + ky + kz) & 1) ? -1.0 : 1.0;
+          const int64_t id = static_cast<int64_t>(zz) * plane + static_cast<int64_t>(yy) * nx + xx;
+          const double w = 3.0 * (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
+          for (int a = 0; a < 3; ++a) {
+            const double ja = sgn * dec<double>(fmom[mom_index(b, 1 + a, id)], b.enc_off[1 + a], b.enc_inv[1 + a]);
+            gJ[a][0] += w * cx * ja;
+            gJ[a][1] += w * cy * ja;
+            gJ[a][2] += w * cz * ja;
+          }
+        }
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) Q[a][c] = -(1.0 / 3.0) / om * (gJ[a][c] + gJ[c][a]);
+  }
   for (int a = 0; a < 3; ++a) {
     double qg = 0;
     for (int c = 0; c < 3; ++c) qg += Q[a][c] * g[c] * b.drho;
@@ -929,78 +1098,93 @@ int grid_for(int64_t n, int threads) {
   return static_cast<int>(g);
 }
 
-template <int BX, int BY, class PR>
+template <int BX, int BY, class PR, bool GC>
 hipError_t launch_fused_t(const BoxDesc* d_boxes, const Item* d_items, int n_items, int grid, int parity,
                           hipStream_t stream) {
-  hipLaunchKernelGGL((fused_step<BX, BY, PR>), dim3(grid), dim3(BX * BY), 0, stream, d_boxes, d_items,
+  hipLaunchKernelGGL((fused_step<BX, BY, PR, GC>), dim3(grid), dim3(BX * BY), 0, stream, d_boxes, d_items,
                      n_items, parity);
   return hipGetLastError();
 }
 
-template <int BX, int BY, class PR>
+template <int BX, int BY, class PR, bool GC>
 int fused_blocks_per_cu_t() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_step<BX, BY, PR>, BX * BY, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_step<BX, BY, PR, GC>, BX * BY, 0) != hipSuccess) return 0;
   return n;
 }
 
-template <int BX, int BY>
+template <int BX, int BY, bool GC>
 int fused_blocks_per_cu_t(int precision) {
   switch (precision) {
-    case kF64: return fused_blocks_per_cu_t<BX, BY, PF64>();
-    case kF32: return fused_blocks_per_cu_t<BX, BY, PF32>();
-    case kF16: return fused_blocks_per_cu_t<BX, BY, PF16>();
-    case kBF16: return fused_blocks_per_cu_t<BX, BY, PBF16>();
+    case kF64: return fused_blocks_per_cu_t<BX, BY, PF64, GC>();
+    case kF32: return fused_blocks_per_cu_t<BX, BY, PF32, GC>();
+    case kF16: return fused_blocks_per_cu_t<BX, BY, PF16, GC>();
+    case kBF16: return fused_blocks_per_cu_t<BX, BY, PBF16, GC>();
     default: return 0;
   }
 }
 
-template <int BX, int BY>
+template <int BX, int BY, bool GC>
 hipError_t launch_fused_t(int precision, const BoxDesc* d_boxes, const Item* d_items, int n_items,
                           int grid, int parity, hipStream_t stream) {
   return dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
-    return launch_fused_t<BX, BY, PR>(d_boxes, d_items, n_items, grid, parity, stream);
+    return launch_fused_t<BX, BY, PR, GC>(d_boxes, d_items, n_items, grid, parity, stream);
   });
 }
 
 }  // namespace
 
-bool fused_config_supported(int precision, int bx, int by) {
-  if (bx == 66 && by == 8) return precision != kF64;  // FP64 needs > 168 VGPRs: would spill
-  return (bx == 32 && by == 8) || (bx == 34 && by == 8) || (bx == 34 && by == 15) || (bx == 18 && by == 14);
+// Tile shapes: (32,8) (34,8) (34,15) for both closures and every precision;
+// (18,14) for the moment closure; (66,8) for the moment closure outside FP64
+// (FP64 needs > 168 VGPRs there: it would spill).
+bool fused_config_supported(int precision, bool gc, int bx, int by) {
+  if ((bx == 32 && by == 8) || (bx == 34 && by == 8) || (bx == 34 && by == 15)) return true;
+  if (gc) return false;
+  if (bx == 18 && by == 14) return true;
+  return bx == 66 && by == 8 && precision != kF64;
 }
 
 size_t phi_bytes(int precision, int64_t n) { return static_cast<size_t>(n) * (precision == kF64 ? 8 : 4); }
-size_t mom_bytes(int precision, int64_t n) {
+size_t mom_bytes(int precision, int64_t n, int nmom) {
   const size_t e = precision == kF64 ? 8 : (precision == kF32 ? 4 : 2);
-  return static_cast<size_t>(n) * 10 * e;
+  return static_cast<size_t>(n) * static_cast<size_t>(nmom) * e;
 }
 
-int fused_blocks_per_cu(int precision, int bx, int by) {
-  if (!fused_config_supported(precision, bx, by)) return 0;
-  if (bx == 32 && by == 8) return fused_blocks_per_cu_t<32, 8>(precision);
-  if (bx == 34 && by == 8) return fused_blocks_per_cu_t<34, 8>(precision);
-  if (bx == 34 && by == 15) return fused_blocks_per_cu_t<34, 15>(precision);
-  if (bx == 18 && by == 14) return fused_blocks_per_cu_t<18, 14>(precision);
-  if (precision == kF32) return fused_blocks_per_cu_t<66, 8, PF32>();
-  if (precision == kF16) return fused_blocks_per_cu_t<66, 8, PF16>();
-  return fused_blocks_per_cu_t<66, 8, PBF16>();
+int fused_blocks_per_cu(int precision, bool gc, int bx, int by) {
+  if (!fused_config_supported(precision, gc, bx, by)) return 0;
+  if (gc) {
+    if (bx == 32 && by == 8) return fused_blocks_per_cu_t<32, 8, true>(precision);
+    if (bx == 34 && by == 8) return fused_blocks_per_cu_t<34, 8, true>(precision);
+    return fused_blocks_per_cu_t<34, 15, true>(precision);
+  }
+  if (bx == 32 && by == 8) return fused_blocks_per_cu_t<32, 8, false>(precision);
+  if (bx == 34 && by == 8) return fused_blocks_per_cu_t<34, 8, false>(precision);
+  if (bx == 34 && by == 15) return fused_blocks_per_cu_t<34, 15, false>(precision);
+  if (bx == 18 && by == 14) return fused_blocks_per_cu_t<18, 14, false>(precision);
+  if (precision == kF32) return fused_blocks_per_cu_t<66, 8, PF32, false>();
+  if (precision == kF16) return fused_blocks_per_cu_t<66, 8, PF16, false>();
+  return fused_blocks_per_cu_t<66, 8, PBF16, false>();
 }
 
-hipError_t launch_fused(int precision, int bx, int by, const BoxDesc* d_boxes, const Item* d_items,
+hipError_t launch_fused(int precision, bool gc, int bx, int by, const BoxDesc* d_boxes, const Item* d_items,
                         int n_items, int grid, int parity, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  if (!fused_config_supported(precision, bx, by)) return hipErrorInvalidValue;
+  if (!fused_config_supported(precision, gc, bx, by)) return hipErrorInvalidValue;
   if (grid <= 0 || grid > n_items) grid = n_items;
-  if (bx == 32 && by == 8) return launch_fused_t<32, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
-  if (bx == 34 && by == 8) return launch_fused_t<34, 8>(precision, d_boxes, d_items, n_items, grid, parity, stream);
-  if (bx == 34 && by == 15) return launch_fused_t<34, 15>(precision, d_boxes, d_items, n_items, grid, parity, stream);
-  if (bx == 18 && by == 14) return launch_fused_t<18, 14>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (gc) {
+    if (bx == 32 && by == 8) return launch_fused_t<32, 8, true>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+    if (bx == 34 && by == 8) return launch_fused_t<34, 8, true>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+    return launch_fused_t<34, 15, true>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  }
+  if (bx == 32 && by == 8) return launch_fused_t<32, 8, false>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 34 && by == 8) return launch_fused_t<34, 8, false>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 34 && by == 15) return launch_fused_t<34, 15, false>(precision, d_boxes, d_items, n_items, grid, parity, stream);
+  if (bx == 18 && by == 14) return launch_fused_t<18, 14, false>(precision, d_boxes, d_items, n_items, grid, parity, stream);
   if (bx == 66 && by == 8) {
-    if (precision == kF32) return launch_fused_t<66, 8, PF32>(d_boxes, d_items, n_items, grid, parity, stream);
-    if (precision == kF16) return launch_fused_t<66, 8, PF16>(d_boxes, d_items, n_items, grid, parity, stream);
-    return launch_fused_t<66, 8, PBF16>(d_boxes, d_items, n_items, grid, parity, stream);
+    if (precision == kF32) return launch_fused_t<66, 8, PF32, false>(d_boxes, d_items, n_items, grid, parity, stream);
+    if (precision == kF16) return launch_fused_t<66, 8, PF16, false>(d_boxes, d_items, n_items, grid, parity, stream);
+    return launch_fused_t<66, 8, PBF16, false>(d_boxes, d_items, n_items, grid, parity, stream);
   }
   return hipErrorInvalidValue;
 }

@@ -16,14 +16,15 @@ constexpr int kFields = 11;  // phi, P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
 struct BoxDesc {
   // ping-pong state buffers, index = parity:
   //   phi[s]: [nz][ny][nx] phase field (storage type of phi)
-  //   mom[s]: [nz][10][ny][nx] moments P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
-  //           (each z plane holds the 10 moment planes back to back)
+  //   mom[s]: [nz][nmom][ny][nx] moments P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
+  //           (each z plane holds its nmom moment planes back to back;
+  //           nmom = 4, P and J only, for the gradient closure)
   void* phi[2];
   void* mom[2];
   int32_t nx, ny, nz;
   int32_t wall[3];        // 1 if the axis has walls
-  int32_t flags;          // LBM_LITERAL_ADVECTION
-  int32_t pad0;
+  int32_t flags;          // LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE
+  int32_t nmom;           // moment fields stored per node: 10, or 4 (gradient closure)
   double rho_g, drho;     // rho = rho_g + phi * drho
   double nu_g, dnu;       // nu = nu_g + phi * dnu
   double beta4;           // 4 beta = 48 sigma / W
@@ -48,16 +49,18 @@ enum Precision { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
 // Fused step over n_items tiles; reads buffer `parity`, writes 1 - parity.
 // grid workgroups loop over the items with stride grid.
-hipError_t launch_fused(int precision, int block_x, int block_y, const BoxDesc* d_boxes,
+// gc selects the gradient-closure kernel (every box of the launch must use it).
+hipError_t launch_fused(int precision, bool gc, int block_x, int block_y, const BoxDesc* d_boxes,
                         const Item* d_items, int n_items, int grid, int parity,
                         hipStream_t stream);
-bool fused_config_supported(int precision, int block_x, int block_y);
+bool fused_config_supported(int precision, bool gc, int block_x, int block_y);
 // Workgroups of the fused kernel that fit on one compute unit at once (0 on error).
-int fused_blocks_per_cu(int precision, int block_x, int block_y);
+int fused_blocks_per_cu(int precision, bool gc, int block_x, int block_y);
 
-// Bytes of the phi and moment arrays of one buffer of a box of n nodes.
+// Bytes of the phi and moment arrays of one buffer of a box of n nodes with
+// nmom moment fields.
 size_t phi_bytes(int precision, int64_t n);
-size_t mom_bytes(int precision, int64_t n);
+size_t mom_bytes(int precision, int64_t n, int nmom);
 
 // Encode N doubles into field `field` (storage of `precision`).
 hipError_t launch_encode(int precision, const BoxDesc& box, int parity, int field,

@@ -42,6 +42,7 @@ struct Box {
 struct lbm_ctx {
   std::vector<Box> boxes;
   int precision = 0;
+  bool gc = false;  // LBM_GRADIENT_CLOSURE (all boxes)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   lbm_device dev{};
@@ -97,6 +98,8 @@ void dev_free(lbm_ctx* c, void* p) {
 
 bool finite(double v) { return std::isfinite(v); }
 
+int nmom_of(const lbm_params& p) { return (p.flags & LBM_GRADIENT_CLOSURE) ? 4 : 10; }
+
 lbm_status validate_box(const lbm_params& p, int idx, int precision0) {
   const char* who = "lbm_create";
   if (p.lattice != LBM_D3Q27) return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: lattice %d unsupported (D3Q27 only)", who, idx, p.lattice);
@@ -110,7 +113,7 @@ lbm_status validate_box(const lbm_params& p, int idx, int precision0) {
   }
   if (p.precision < LBM_FP64 || p.precision > LBM_BF16_OS) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: precision %d invalid", who, idx, p.precision);
   if (p.precision != precision0) return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: all boxes of a context must share one precision", who, idx);
-  if (p.flags & ~LBM_LITERAL_ADVECTION) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: unknown flags 0x%x", who, idx, p.flags);
+  if (p.flags & ~(LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: unknown flags 0x%x", who, idx, p.flags);
   if (!(finite(p.rho_l) && p.rho_l > 0 && finite(p.rho_g) && p.rho_g > 0)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: densities must be finite and > 0", who, idx);
   if (!(finite(p.nu_l) && p.nu_l > 0 && finite(p.nu_g) && p.nu_g > 0)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: viscosities must be finite and > 0 (tau > 1/2)", who, idx);
   if (!(finite(p.sigma) && p.sigma >= 0)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: sigma must be finite and >= 0", who, idx);
@@ -128,6 +131,7 @@ void fill_desc(Box& b, int precision) {
   d.nz = p.nz;
   for (int a = 0; a < 3; ++a) d.wall[a] = p.bc[a] == LBM_WALL ? 1 : 0;
   d.flags = p.flags;
+  d.nmom = nmom_of(p);
   d.rho_g = p.rho_g;
   d.drho = p.rho_l - p.rho_g;
   d.nu_g = p.nu_g;
@@ -225,7 +229,7 @@ hipError_t enqueue_steps(lbm_ctx* c, int nsteps, int parity0) {
   int parity = parity0;
   const int grid = c->tuning.persistent > 0 ? std::min(c->tuning.persistent, c->n_items) : c->n_items;
   for (int s = 0; s < nsteps; ++s) {
-    hipError_t e = lbm::launch_fused(c->precision, c->tuning.block_x, c->tuning.block_y, c->d_boxes,
+    hipError_t e = lbm::launch_fused(c->precision, c->gc, c->tuning.block_x, c->tuning.block_y, c->d_boxes,
                                      c->d_items, c->n_items, grid, parity, c->stream);
     if (e != hipSuccess) return e;
     parity ^= 1;
@@ -316,6 +320,8 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
     for (int i = 0; i < n_boxes; ++i) {
       lbm_status s = validate_box(boxes[i], i, boxes[0].precision);
       if (s != LBM_OK) return s;
+      if ((boxes[i].flags ^ boxes[0].flags) & LBM_GRADIENT_CLOSURE)
+        return fail(nullptr, LBM_ERR_UNSUPPORTED, "lbm_create: box %d: all boxes of a context must share one closure", i);
     }
     if (dev && ((dev->alloc == nullptr) != (dev->free == nullptr)))
       return fail(nullptr, LBM_ERR_ARG, "lbm_create: alloc and free callbacks must be given together");
@@ -323,6 +329,7 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
     lbm_ctx* c = new lbm_ctx();
     if (dev) c->dev = *dev;
     c->precision = boxes[0].precision;
+    c->gc = (boxes[0].flags & LBM_GRADIENT_CLOSURE) != 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) {
       delete c;
@@ -345,7 +352,7 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
       b.n = static_cast<int64_t>(b.prm.nx) * b.prm.ny * b.prm.nz;
       default_encoding(b);
       const size_t pb = align256(lbm::phi_bytes(c->precision, b.n));
-      const size_t total = pb + align256(lbm::mom_bytes(c->precision, b.n));
+      const size_t total = pb + align256(lbm::mom_bytes(c->precision, b.n, nmom_of(b.prm)));
       for (int s = 0; s < 2; ++s) {
         b.mem[s] = dev_alloc(c, total);
         if (!b.mem[s]) {
@@ -484,7 +491,7 @@ lbm_status lbm_step_unbatched(lbm_ctx* c, int32_t nsteps) {
     if (!c->boxes[i].initialized) return fail(c, LBM_ERR_STATE, "lbm_step_unbatched: box %zu not initialised", i);
   for (int s = 0; s < nsteps; ++s) {
     for (auto& bi : c->box_items) {
-      HIP_TRY(c, lbm::launch_fused(c->precision, c->tuning.block_x, c->tuning.block_y, c->d_boxes,
+      HIP_TRY(c, lbm::launch_fused(c->precision, c->gc, c->tuning.block_x, c->tuning.block_y, c->d_boxes,
                                    c->d_items + bi.first, bi.second, bi.second, c->parity, c->stream));
     }
     c->parity ^= 1;
@@ -566,7 +573,7 @@ lbm_status lbm_set_encoding(lbm_ctx* c, int32_t box, const double* offset, const
 lbm_status lbm_set_tuning(lbm_ctx* c, const lbm_tuning* t) {
   if (!c) return fail(nullptr, LBM_ERR_ARG, "NULL context");
   if (!t) return fail(c, LBM_ERR_ARG, "lbm_set_tuning: NULL tuning");
-  if (!lbm::fused_config_supported(c->precision, t->block_x, t->block_y)) return fail(c, LBM_ERR_UNSUPPORTED, "lbm_set_tuning: block %dx%d unsupported for this precision", t->block_x, t->block_y);
+  if (!lbm::fused_config_supported(c->precision, c->gc, t->block_x, t->block_y)) return fail(c, LBM_ERR_UNSUPPORTED, "lbm_set_tuning: block %dx%d unsupported for this precision and closure", t->block_x, t->block_y);
   if (t->z_chunk < 1) return fail(c, LBM_ERR_ARG, "lbm_set_tuning: z_chunk must be >= 1");
   if (t->persistent < 0) return fail(c, LBM_ERR_ARG, "lbm_set_tuning: persistent must be >= 0");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -609,9 +616,9 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
   const bool graphs = c->graphs;
   c->graphs = true;
   for (auto& sh : shapes) {
-    if (!lbm::fused_config_supported(c->precision, sh[0], sh[1])) continue;
+    if (!lbm::fused_config_supported(c->precision, c->gc, sh[0], sh[1])) continue;
     std::vector<int> zcs = fixed_zcs;
-    const int slots = cus * lbm::fused_blocks_per_cu(c->precision, sh[0], sh[1]);
+    const int slots = cus * lbm::fused_blocks_per_cu(c->precision, c->gc, sh[0], sh[1]);
     for (int rounds = 1; slots > 0 && rounds <= 4; ++rounds) {
       const int zc = wave_balanced_chunk(c, sh[0] - 2, sh[1] - 2, static_cast<int64_t>(rounds) * slots, maxz);
       if (zc >= 4 && std::find(zcs.begin(), zcs.end(), zc) == zcs.end()) zcs.push_back(zc);
@@ -650,7 +657,7 @@ lbm_status lbm_synchronize(lbm_ctx* c) {
 
 double lbm_bytes_per_update(const lbm_ctx* c) {
   if (!c) return 0.0;
-  return 2.0 * static_cast<double>(lbm::phi_bytes(c->precision, 1) + lbm::mom_bytes(c->precision, 1));
+  return 2.0 * static_cast<double>(lbm::phi_bytes(c->precision, 1) + lbm::mom_bytes(c->precision, 1, c->gc ? 4 : 10));
 }
 
 int64_t lbm_total_nodes(const lbm_ctx* c) {

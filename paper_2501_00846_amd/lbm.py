@@ -25,6 +25,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ER
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16_os": 2, "bf16_os": 3}
 PERIODIC, WALL = 0, 1
 LITERAL_ADVECTION = 1
+GRADIENT_CLOSURE = 2
 FIELDS = ("phi", "P", "Jx", "Jy", "Jz", "Qxx", "Qyy", "Qzz", "Qxy", "Qxz", "Qyz")
 
 
@@ -142,7 +143,8 @@ def make_params(prob, precision="fp64"):
         p.bc[a] = int(prob.bc[a])
         p.gravity[a] = float(prob.gravity[a])
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    p.flags = LITERAL_ADVECTION if getattr(prob, "literal_advection", False) else 0
+    p.flags = (LITERAL_ADVECTION if getattr(prob, "literal_advection", False) else 0) | \
+        (GRADIENT_CLOSURE if getattr(prob, "gradient_closure", False) else 0)
     p.rho_l, p.rho_g = float(prob.rho_l), float(prob.rho_g)
     p.nu_l, p.nu_g = float(prob.nu_l), float(prob.nu_g)
     p.sigma, p.mobility, p.width = float(prob.sigma), float(prob.mobility), float(prob.width)
