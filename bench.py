@@ -54,6 +54,12 @@ def make_cases(config):
         return WL.ensemble(64), "ensemble of 64 periodic droplet boxes, edges in [24, 96]"
     if config == "C5":
         return [WL.drop_into_pool()], "drop into pool 512^3, walls on +-z, rho ratio 1000, mu ratio 100"
+    if config == "raindrop":
+        return [WL.raindrop_train(dtype=np.float32)], ("train of 5 drops onto a substrate, 500x500x3000, walls on "
+                                                       "+-z, We 40, rho ratio 1000, mu ratio 100")
+    if config == "eoga":
+        return WL.eo_ga_sweep(), ("Eo-Ga rising-bubble sweep: 12 periodic 200x200x400 boxes in one launch, "
+                                  "rho ratio 1000, mu ratio 100")
     raise SystemExit("unknown config " + config)
 
 
@@ -161,6 +167,14 @@ def cpu_baseline(config):
         case = WL.ensemble_box(0)
         sample = "ensemble box 0 (%dx%dx%d), 10 steps" % (case.problem.nx, case.problem.ny, case.problem.nz)
         nsteps = 10
+    elif config == "raindrop":
+        case = WL.raindrop_train(nx=64, ny=64, nz=240, radius=8.0)
+        sample = "raindrop train scaled to 64x64x240 (R 8), 2 steps"
+        nsteps = 2
+    elif config == "eoga":
+        case = WL.eo_ga_bubble(30.0, 100.0, nx=64, ny=64, nz=128, radius=16.0)
+        sample = "one Eo-Ga bubble (Eo 30, Ga 100) scaled to 64x64x128 (R 16), 2 steps"
+        nsteps = 2
     else:
         n = 96
         if config == "C3":
@@ -316,7 +330,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C4", "C5", "raindrop", "eoga"])
     ap.add_argument("--precision", default=None,
                     help="comma list of fp64,fp32,fp16_os,bf16_os (default depends on config)")
     ap.add_argument("--no-tune", action="store_true")
@@ -356,7 +370,7 @@ def main():
         sys.exit(2)
 
     defaults = {"C1": "fp64", "C2": "fp64,fp32", "C3": "fp32,fp16_os,bf16_os", "C4": "fp32",
-                "C5": "fp32,fp16_os,fp64"}
+                "C5": "fp32,fp16_os,fp64", "raindrop": "fp32", "eoga": "fp32"}
     precisions = (args.precision or defaults[args.config]).split(",")
     log("bench: building cases for %s" % args.config)
     cases, desc = make_cases(args.config)

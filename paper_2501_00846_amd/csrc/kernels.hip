@@ -265,6 +265,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
   constexpr int PX = BX + 2;
   constexpr int PY = BY + 2;
   constexpr int NM = GC ? 4 : 10;  // moment fields per plane
+  constexpr int NL = GC ? 1 : 10;  // of them loaded per lane (the closure takes J from its LDS patch)
   __shared__ FusedShared<BX, BY, PR, GC> sh;
 
   const int tid = threadIdx.x;
@@ -409,8 +410,8 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         }
       }
     };
-    // F[a] = (s_x s_y J_a, s_y d_x J_a, s_x d_y J_a)
-    auto filter_J = [&](R (*F)[3]) {
+    // F[a] = (s_x s_y J_a, s_y d_x J_a, s_x d_y J_a, J_a at the centre)
+    auto filter_J = [&](R (*F)[4]) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         R dx[3], sx[3];
@@ -420,6 +421,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
           const R l = row[0], c = row[1], h = row[2];
           dx[r] = h - l;
           sx[r] = l + R(4) * c + h;
+          if (r == 1) F[a][3] = c;
         }
         F[a][0] = sx[0] + R(4) * sx[1] + sx[2];
         F[a][1] = dx[0] + R(4) * dx[1] + dx[2];
@@ -428,7 +430,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     };
 
     R Fm[4], F0[4], Fp[4];
-    R JFm[GC ? 3 : 1][3], JF0[GC ? 3 : 1][3], JFp[GC ? 3 : 1][3];
+    R JFm[GC ? 3 : 1][4], JF0[GC ? 3 : 1][4], JFp[GC ? 3 : 1][4];
     R jnxt[GC ? 3 : 1][NPH];
     stage_phi(p_first - 1);
     if constexpr (GC) {
@@ -450,11 +452,11 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     __syncthreads();
 
     // moments of the own column, prefetched one plane ahead
-    R nxt[NM];
+    R nxt[NL];
     auto load_moments = [&](int q, R* m) {
       const gptr<const char> base = (gptr<const char>)s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * NM * plane_bm;
 #pragma unroll
-      for (int k = 0; k < NM; ++k)
+      for (int k = 0; k < NL; ++k)
         m[k] = dec<R>(*(gptr<const TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), b.enc_off[k], b.enc_inv[k]);
     };
     load_moments(p_first, nxt);
@@ -469,7 +471,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     // every store.
     auto settle_prefetch = [&]() {
 #pragma unroll
-      for (int k = 0; k < NM; ++k) asm volatile("" ::"v"(nxt[k]));
+      for (int k = 0; k < NL; ++k) asm volatile("" ::"v"(nxt[k]));
 #pragma unroll
       for (int j = 0; j < NPH; ++j) asm volatile("" ::"v"(phinxt[j]));
       if constexpr (GC) {
@@ -511,9 +513,9 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     };
 
     for (int p = p_first; p <= p_last; ++p) {
-      R cur[NM];
+      R cur[NL];
 #pragma unroll
-      for (int k = 0; k < NM; ++k) cur[k] = nxt[k];
+      for (int k = 0; k < NL; ++k) cur[k] = nxt[k];
       if (p < p_last) load_moments(p + 1, nxt);
 
       // (A) phi plane p+1 (prefetched) -> LDS -> filtered registers; prefetch p+2
@@ -541,7 +543,19 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R gmy = gcy ? -gy : gy;
 
       const R P = cur[0];
-      const R Jx = cur[1], Jy = cur[2], Jz = cur[3];
+      R Jx, Jy, Jz;
+      if constexpr (GC) {
+        // own J from the centre of the staged patch, which a ghost lane holds
+        // with the sign (-1)^(walls crossed)
+        const R so = (gcx != gcy) ? R(-1) : R(1);
+        Jx = so * JF0[0][3];
+        Jy = so * JF0[1][3];
+        Jz = so * JF0[2][3];
+      } else {
+        Jx = cur[1 % NL];
+        Jy = cur[2 % NL];
+        Jz = cur[3 % NL];
+      }
 
       // density, viscosity and relaxation interpolation in FP64 (Sec. II.C),
       // evaluated at phi clamped to the model's range [0, 1]
@@ -588,12 +602,12 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         Txz = ca * (gJ[0][2] + gJ[2][0]);
         Tyz = ca * (gJ[1][2] + gJ[2][1]);
       } else {
-        Txx = cur[4 % NM];
-        Tyy = cur[5 % NM];
-        Tzz = cur[6 % NM];
-        Txy = cur[7 % NM];
-        Txz = cur[8 % NM];
-        Tyz = cur[9 % NM];
+        Txx = cur[4 % NL];
+        Tyy = cur[5 % NL];
+        Tzz = cur[6 % NL];
+        Txy = cur[7 % NL];
+        Txz = cur[8 % NL];
+        Tyz = cur[9 % NL];
       }
 
       // chemical potential and the force per unit mass a = F / rho
@@ -836,7 +850,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
+          for (int k = 0; k < 4; ++k) {
             JFm[a][k] = JF0[a][k];
             JF0[a][k] = JFp[a][k];
           }

@@ -216,6 +216,91 @@ def drop_into_pool(n=512, pool_depth=128, radius=40.0, zc=260.0, seed=5,
     return Case("drop_into_pool_%dx%dx%d" % (nx, ny, nz), prob, phi, u, None, seed)
 
 
+def raindrop_train(nx=500, ny=500, nz=3000, n_drops=5, radius=25.0, spacing=2.0,
+                   weber=40.0, speed=0.05, z_first=None, seed=6, rho_ratio=1000.0,
+                   mu_ratio=100.0, nu_gas=1.0 / 6.0, mobility=0.05, width=4.0, g=1e-6,
+                   dtype=np.float64):
+    """A train of drops falling onto a solid substrate (Sec. III.D).
+
+    No-slip walls on -z (the substrate) and +z, periodic x and y; the mirror
+    ghosts of the phase field make the walls impermeable and neutrally wetting.
+    Drop k (k = 0 nearest the substrate) of diameter D = 2 radius is centred
+    at z_first + k * spacing * D over the middle of the box (seeded jitter of
+    +-0.5 cells in x and y), moving down at `speed` under gravity g; the
+    surface tension gives the Weber number We = rho_l speed^2 D / sigma.  The
+    default box is the paper's 500 x 500 x 3000 with five drops two diameters
+    apart.  M = 0.05 keeps the cell Peclet number of the phase-field advection
+    at speed / M = 1.
+    """
+    rng = np.random.default_rng(seed)
+    diam = 2.0 * radius
+    z_first = radius + diam if z_first is None else z_first
+    jit = rng.uniform(-0.5, 0.5, size=(n_drops, 2))
+    x = np.arange(nx, dtype=dtype).reshape(1, 1, nx)
+    y = np.arange(ny, dtype=dtype).reshape(1, ny, 1)
+    phi = np.zeros((nz, ny, nx), dtype=dtype)
+    reach = radius + 10.0 * width  # tanh tail below 1e-17 beyond this distance
+    for k in range(n_drops):
+        cz = z_first + k * spacing * diam
+        z0, z1 = max(0, int(cz - reach)), min(nz, int(cz + reach) + 1)
+        if z0 >= z1:
+            continue
+        z = np.arange(z0, z1, dtype=dtype).reshape(-1, 1, 1)
+        r = np.sqrt((x - ((nx - 1) / 2 + jit[k, 0])) ** 2 + (y - ((ny - 1) / 2 + jit[k, 1])) ** 2
+                    + (z - cz) ** 2)
+        np.maximum(phi[z0:z1], tanh_profile(radius - r, width).astype(dtype), out=phi[z0:z1])
+    u = np.zeros((3,) + phi.shape, dtype=dtype)
+    u[2] = -speed * phi
+    rho_l, rho_g = 1.0, 1.0 / rho_ratio
+    nu_l = nu_gas * mu_ratio / rho_ratio
+    sigma = rho_l * speed ** 2 * diam / weber
+    prob = Problem(nx, ny, nz, (PERIODIC, PERIODIC, WALL), rho_l, rho_g, nu_l, nu_gas,
+                   sigma, mobility, width, (0.0, 0.0, -g), rho_g)
+    return Case("raindrop_train_%dx%dx%d" % (nx, ny, nz), prob, phi, u, None, seed)
+
+
+# Eo-Ga points of the deformation-regime sweep (Sec. III.A); (30, 100) is the
+# peripheral-breakup case the paper names
+EO_GA_POINTS = [(eo, ga) for eo in (1.0, 10.0, 30.0, 100.0) for ga in (10.0, 30.0, 100.0)]
+
+
+def eo_ga_bubble(eotvos, galilei, nx=200, ny=200, nz=400, radius=50.0, g=4e-6, seed=7,
+                 rho_ratio=1000.0, mu_ratio=100.0, width=4.0, mobility=0.05):
+    """Gas bubble of the Eo-Ga deformation-regime sweep (Sec. III.A).
+
+    Periodic in every direction; D = 100 in a 200 x 200 x 400 box by default.
+    sigma from Eo = rho_l g R^2 / sigma, the liquid viscosity from
+    Ga = sqrt(g R) R / nu_l, the gas viscosity from the dynamic viscosity
+    ratio; buoyancy on the light phase only (rho_ref = rho_l).  Seeded jitter
+    of +-0.5 cells of the centre, which sits a quarter of the box height up.
+    The paper does not give g; g = 4e-6 keeps sigma <= 0.01 down to Eo = 1 at
+    R = 50 (with g = 5e-5, Eo = 1 needs sigma = 0.125, and that box loses
+    stability within a few hundred steps at density ratio 1000).
+    """
+    rng = np.random.default_rng(seed)
+    j = rng.uniform(-0.5, 0.5, size=3)
+    c = ((nx - 1) / 2 + j[0], (ny - 1) / 2 + j[1], nz / 4 + j[2])
+    x = np.arange(nx, dtype=np.float64).reshape(1, 1, nx)
+    y = np.arange(ny, dtype=np.float64).reshape(1, ny, 1)
+    z = np.arange(nz, dtype=np.float64).reshape(nz, 1, 1)
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+    phi = tanh_profile(r - radius, width)
+    rho_l, rho_g = 1.0, 1.0 / rho_ratio
+    sigma = rho_l * g * radius ** 2 / eotvos
+    nu_l = np.sqrt(g * radius) * radius / galilei
+    nu_g = nu_l * rho_ratio / mu_ratio
+    prob = Problem(nx, ny, nz, (PERIODIC,) * 3, rho_l, rho_g, nu_l, nu_g, sigma, mobility,
+                   width, (0.0, 0.0, -g), rho_l)
+    return Case("eo_ga_bubble_Eo%g_Ga%g" % (eotvos, galilei), prob, phi, None, None, seed)
+
+
+def eo_ga_sweep(points=None, **kw):
+    """One bubble per (Eo, Ga) point, seeds 7, 8, ...; equal boxes, so the
+    whole sweep runs as one batched launch per step."""
+    pts = EO_GA_POINTS if points is None else points
+    return [eo_ga_bubble(eo, ga, seed=7 + i, **kw) for i, (eo, ga) in enumerate(pts)]
+
+
 def random_state(nx, ny, nz, seed, bc=(PERIODIC,) * 3, amp_u=0.02, amp_p=0.01,
                  amp_q=1e-3, **kw):
     """Smooth-ish random state for invariance and parity tests.
