@@ -27,7 +27,8 @@
 //       columns and adds their moments to the running sums of output planes
 //       p-1, p, p+1 (registers), and likewise the divergence of G.  Output
 //       plane p-1 is then complete: Q' = Pi - cs^2 P' I - J' J', the FTCS
-//       phase update phi' = phi + M lap(phi) - div(G), and 11 stores.
+//       phase update phi' = phi + M lap(phi) - div(G), and 11 stores (5
+//       with the gradient closure, see fused_step).
 // Halo work is recomputed by the halo-ring threads; nothing but the 11 state
 // fields goes to or comes from HBM.
 //
@@ -241,9 +242,9 @@ struct FusedShared {
 // ---------------------------------------------------------------------------
 // The fused step
 // ---------------------------------------------------------------------------
-// Occupancy targets: FP64 needs ~235 VGPRs (2 waves per SIMD); the FP32
+// Occupancy targets: FP64 needs 210-256 VGPRs (2 waves per SIMD); the FP32
 // arithmetic instantiations are held to 128 VGPRs for 4 waves per SIMD (the
-// few spills this costs sit outside the z loop).
+// moment closure fits; the gradient closure spills a few registers).
 template <class PR> struct WavesPerEU { static constexpr int v = 4; };
 template <> struct WavesPerEU<PF64> { static constexpr int v = 2; };
 
