@@ -159,6 +159,27 @@ __host__ __device__ constexpr int fslot(int cx, int cy, int cz) {
   return (((cy + 1) * 3 + (cx + 1)) - ((((cy + 1) * 3 + (cx + 1)) > 4) ? 1 : 0)) * 3 + (cz + 1);
 }
 
+// x-y parts of the isotropic divergence of a flux stored per tile position:
+// hx = sum_cy w(cy) (G_x(+1, cy) - G_x(-1, cy)), hy likewise along y, and
+// hz = sum w(cx) w(cy) G_z(cx, cy), weights w = (1, 4, 1); each sum starts from
+// its first term.
+template <class R, class F>
+__device__ __forceinline__ void div_sums(const F& G, R& hx, R& hy, R& hz) {
+  hx = G(0, 1, -1) - G(0, -1, -1);
+  hx += R(4) * (G(0, 1, 0) - G(0, -1, 0));
+  hx += G(0, 1, 1) - G(0, -1, 1);
+  hy = G(1, -1, 1) - G(1, -1, -1);
+  hy += R(4) * (G(1, 0, 1) - G(1, 0, -1));
+  hy += G(1, 1, 1) - G(1, 1, -1);
+  hz = G(2, -1, -1);
+#pragma unroll
+  for (int k = 1; k < 9; ++k) {
+    const int cx = k % 3 - 1, cy = k / 3 - 1;
+    const R w = (cx == 0 ? R(4) : R(1)) * (cy == 0 ? R(4) : R(1));
+    hz += w * G(2, cx, cy);
+  }
+}
+
 // Moment accumulator of one output plane: P, J (3), Pi = sum f c c (6).
 template <class R> struct Acc {
   R p, jx, jy, jz, xx, yy, zz, xy, xz, yz;
@@ -166,7 +187,9 @@ template <class R> struct Acc {
 };
 
 // Add the moments of 9 populations v[(cy+1)*3 + (cx+1)] sharing c_z = cz.
-template <class R, int CZ>
+// FRESH: the accumulator holds nothing yet, so the sums are assigned (adding
+// them to zero would cost an instruction each: x + 0 is not x for x = -0).
+template <class R, int CZ, bool FRESH = false>
 __device__ __forceinline__ void accum_group(const R* v, Acc<R>& a) {
   // along x for each c_y row: s0 = sum, s1 = sum cx, s2 = sum cx^2
   R s0[3], s1[3], s2[3];
@@ -183,6 +206,20 @@ __device__ __forceinline__ void accum_group(const R* v, Acc<R>& a) {
   const R m10 = s1[0] + s1[1] + s1[2];
   const R m11 = s1[2] - s1[0];
   const R m20 = s2[0] + s2[1] + s2[2];
+  if constexpr (FRESH) {
+    static_assert(CZ > 0, "only the group entering a new output plane starts it");
+    a.p = m00;
+    a.jx = m10;
+    a.jy = m01;
+    a.xx = m20;
+    a.yy = m02;
+    a.xy = m11;
+    a.zz = m00;
+    a.jz = m00;
+    a.xz = m10;
+    a.yz = m01;
+    return;
+  }
   a.p += m00;
   a.jx += m10;
   a.jy += m01;
@@ -666,15 +703,17 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       // evaluate w(c) g(c) at the 27 velocities: x, then y, then z, with the
       // one-dimensional weights (1, 4, 1) (x 1/216 folded in above)
       auto xb = [](R c0, R c1, R c2, R* o) { o[0] = c0 - c1 + c2; o[1] = R(4) * c0; o[2] = c0 + c1 + c2; };
+      auto xb2 = [](R c0, R c1, R* o) { o[0] = c0 - c1; o[1] = R(4) * c0; o[2] = c0 + c1; };
+      auto xb1 = [](R c0, R* o) { o[0] = c0; o[1] = R(4) * c0; o[2] = c0; };
       R B00[3], B01[3], B02[3], B10[3], B11[3], B12[3], B20[3], B21[3];
       xb(G0, Gx, Gxx, B00);
       xb(Gy, Gxy, Gxxy, B01);
-      xb(Gyy, Gyyx, R(0), B02);
+      xb2(Gyy, Gyyx, B02);
       xb(Gz, Gxz, Gxxz, B10);
-      xb(Gyz, Gxyz, R(0), B11);
-      xb(Gyyz, R(0), R(0), B12);
-      xb(Gzz, Gzzx, R(0), B20);
-      xb(Gzzy, R(0), R(0), B21);
+      xb2(Gyz, Gxyz, B11);
+      xb1(Gyyz, B12);
+      xb2(Gzz, Gzzx, B20);
+      xb1(Gzzy, B21);
       R fo[3];  // own column (cx, cy) = (0, 0), cz = -1, 0, 1
 #pragma unroll
       for (int cyi = 0; cyi < 3; ++cyi) {
@@ -737,7 +776,6 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 
       // (C) pull, accumulate, finalise output plane p-1
       if (out_col) {
-        accP.zero();
         const bool zb_lo = wz && p == 0;
         const bool zb_hi = wz && p == nz - 1;
         // regular pulls from the 3 x 3 neighbour columns
@@ -752,7 +790,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
           }
           if (czi == 0) accum_group<R, -1>(v, accM);
           else if (czi == 1) accum_group<R, 0>(v, acc0);
-          else accum_group<R, 1>(v, accP);
+          else accum_group<R, 1, true>(v, accP);
         }
         // half-way bounce-back into this node (plane p): direction c pulls from
         // behind a wall when the node is on that wall's side, and then takes
@@ -783,50 +821,16 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         // divergence of the phase-field flux (forward neighbours x + c)
         {
           auto G = [&](int comp, int cx, int cy) { return sh.g[comp * NT + sp + cy * BX + cx]; };
-          R hx = R(0), hy = R(0), hz = R(0);
-#pragma unroll
-          for (int cy = -1; cy <= 1; ++cy) {
-            const R wyv = cy == 0 ? R(4) : R(1);
-            hx += wyv * (G(0, 1, cy) - G(0, -1, cy));
-          }
-#pragma unroll
-          for (int cx = -1; cx <= 1; ++cx) {
-            const R wxv = cx == 0 ? R(4) : R(1);
-            hy += wxv * (G(1, cx, 1) - G(1, cx, -1));
-          }
-#pragma unroll
-          for (int cy = -1; cy <= 1; ++cy) {
-#pragma unroll
-            for (int cx = -1; cx <= 1; ++cx) {
-              const R w = (cx == 0 ? R(4) : R(1)) * (cy == 0 ? R(4) : R(1));
-              hz += w * G(2, cx, cy);
-            }
-          }
+          R hx, hy, hz;
+          div_sums(G, hx, hy, hz);
           const R hxy = hx + hy;
           dM += hxy + hz;
           d0 += R(4) * hxy;
           dP = hxy - hz;
           if (zb_lo || zb_hi) {
             auto GG = [&](int comp, int cx, int cy) { return sh.gg[comp * NT + sp + cy * BX + cx]; };
-            R gx2 = R(0), gy2 = R(0), gz2 = R(0);
-#pragma unroll
-            for (int cy = -1; cy <= 1; ++cy) {
-              const R wyv = cy == 0 ? R(4) : R(1);
-              gx2 += wyv * (GG(0, 1, cy) - GG(0, -1, cy));
-            }
-#pragma unroll
-            for (int cx = -1; cx <= 1; ++cx) {
-              const R wxv = cx == 0 ? R(4) : R(1);
-              gy2 += wxv * (GG(1, cx, 1) - GG(1, cx, -1));
-            }
-#pragma unroll
-            for (int cy = -1; cy <= 1; ++cy) {
-#pragma unroll
-              for (int cx = -1; cx <= 1; ++cx) {
-                const R w = (cx == 0 ? R(4) : R(1)) * (cy == 0 ? R(4) : R(1));
-                gz2 += w * GG(2, cx, cy);
-              }
-            }
+            R gx2, gy2, gz2;
+            div_sums(GG, gx2, gy2, gz2);
             // plane -1 feeds output 0 with (Hxy - Hz); plane nz feeds nz-1 with (Hxy + Hz)
             if (zb_lo) d0 += (gx2 + gy2) - gz2;
             if (zb_hi) d0 += (gx2 + gy2) + gz2;
