@@ -80,13 +80,17 @@ def measured_traffic(config, precision, tuning):
         return None
     with open(path) as fh:
         data = json.load(fh)
-    ent = data.get("%s/%s" % (config, precision))
+    launch = [tuning[k] for k in ("block_x", "block_y", "z_chunk")]
+    ent = data.get(traffic_key(config, precision, launch))
     if not ent or ent.get("kernel_hash") != kernel_hash():
         return None
-    launch = [tuning[k] for k in ("block_x", "block_y", "z_chunk")]
-    if ent.get("tuning") is not None and ent["tuning"][:3] != launch:
-        return None
     return ent["bytes_per_launch"]
+
+
+def traffic_key(config, precision, launch):
+    """Entry name in profiles/traffic.json: workload, closure and precision
+    (config is e.g. "C2" or "C5/gc"), then tile shape and z-chunk."""
+    return "%s/%s@%s" % (config, precision, ",".join(str(v) for v in launch[:3]))
 
 
 def copy_bandwidth(nbytes=1 << 31, reps=10):
@@ -332,7 +336,9 @@ def summarize_counters(args):
     # algorithmic bytes per update: phi + moment fields, read and written
     bpl = 2 * ({"fp64": 8, "fp32": 4}.get(prec, 4) + (4 if gc else 10) * {"fp64": 8, "fp32": 4}.get(prec, 2))
     tuning = [int(v) for v in args.tuning.split(",")] if args.tuning else None
-    key = "%s%s/%s" % (args.config, "/gc" if gc else "", prec)
+    if tuning is None:
+        raise SystemExit("--summarize-counters needs the --tuning the counters were taken with")
+    key = traffic_key(args.config + ("/gc" if gc else ""), prec, tuning)
     data[key] = {
         "kernel_hash": kernel_hash(), "tuning": tuning,
         "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,

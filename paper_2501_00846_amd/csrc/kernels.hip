@@ -148,6 +148,19 @@ __device__ __forceinline__ uint32_t lane_off(uint32_t v) {
   return v;
 }
 
+// Store of a freshly computed output element, with the non-temporal hint when
+// NT is set: the next step reads the element back only after the whole state
+// has streamed through the caches, and the hint keeps it from displacing the
+// halo lines that neighbouring tiles re-read.  The offset-scale modes (2-byte
+// moments) keep the default policy for all their fields: the rows of their
+// tiles only partly cover 64 B segments, and partial non-temporal writes are
+// much slower.
+template <bool NT, class T>
+__device__ __forceinline__ void store_out(gptr<T> p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Plane index map for a uniform q in [-2, n+1]: fast path inside the domain.
 __device__ __forceinline__ int map_plane(int q, int n, int wall) {
   if (q >= 0 && q < n) return q;
@@ -304,6 +317,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
   constexpr int PY = BY + 2;
   constexpr int NM = GC ? 4 : 10;  // moment fields per plane
   constexpr int NL = GC ? 1 : 10;  // of them loaded per lane (the closure takes J from its LDS patch)
+  constexpr bool NTS = sizeof(TM) >= 4;  // non-temporal output stores (FP64, FP32 storage)
   __shared__ FusedShared<BX, BY, PR, GC> sh;
 
   const int tid = threadIdx.x;
@@ -543,11 +557,12 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R q_xz = a.xz - a.jx * a.jz;
       const R q_yz = a.yz - a.jy * a.jz;
       const R phin = phic + mob * lapc - advc - d * R(1.0 / 72.0);
-      *(gptr<TP>)(sbase((gptr<char>)d_phi_g + static_cast<int64_t>(Z) * plane_bp) + lane_off(voff_p)) = Enc<TP>::go(phin, 0.f, 1.f);
+      store_out<NTS>((gptr<TP>)(sbase((gptr<char>)d_phi_g + static_cast<int64_t>(Z) * plane_bp) + lane_off(voff_p)),
+                Enc<TP>::go(phin, 0.f, 1.f));
       const R mv[10] = {P, a.jx, a.jy, a.jz, q_xx, q_yy, q_zz, q_xy, q_xz, q_yz};
 #pragma unroll
       for (int k = 0; k < NM; ++k)
-        *(gptr<TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)) = Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]);
+        store_out<NTS>((gptr<TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]));
     };
 
     for (int p = p_first; p <= p_last; ++p) {
