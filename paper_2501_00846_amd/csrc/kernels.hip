@@ -151,10 +151,11 @@ __device__ __forceinline__ uint32_t lane_off(uint32_t v) {
 // Store of a freshly computed output element, with the non-temporal hint when
 // NT is set: the next step reads the element back only after the whole state
 // has streamed through the caches, and the hint keeps it from displacing the
-// halo lines that neighbouring tiles re-read.  The offset-scale modes (2-byte
-// moments) keep the default policy for all their fields: the rows of their
-// tiles only partly cover 64 B segments, and partial non-temporal writes are
-// much slower.
+// halo lines that neighbouring tiles re-read.  The hint pays only where a
+// wave's stores cover whole 64-byte segments; on partly covered segments
+// non-temporal writes are several times slower, so the kernel uses it only
+// for 4- and 8-byte storage, tiles whose lanes store whole aligned rows, and
+// boxes whose rows start on 64-byte boundaries.
 template <bool NT, class T>
 __device__ __forceinline__ void store_out(gptr<T> p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
@@ -317,7 +318,9 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
   constexpr int PY = BY + 2;
   constexpr int NM = GC ? 4 : 10;  // moment fields per plane
   constexpr int NL = GC ? 1 : 10;  // of them loaded per lane (the closure takes J from its LDS patch)
-  constexpr bool NTS = sizeof(TM) >= 4;  // non-temporal output stores (FP64, FP32 storage)
+  // non-temporal output stores possible: FP64 / FP32 storage and the
+  // interior-first lane map (32 output columns per row)
+  constexpr bool NTS = sizeof(TM) >= 4 && (BX - 2) % 32 == 0;
   __shared__ FusedShared<BX, BY, PR, GC> sh;
 
   const int tid = threadIdx.x;
@@ -557,12 +560,21 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R q_xz = a.xz - a.jx * a.jz;
       const R q_yz = a.yz - a.jy * a.jz;
       const R phin = phic + mob * lapc - advc - d * R(1.0 / 72.0);
-      store_out<NTS>((gptr<TP>)(sbase((gptr<char>)d_phi_g + static_cast<int64_t>(Z) * plane_bp) + lane_off(voff_p)),
-                Enc<TP>::go(phin, 0.f, 1.f));
       const R mv[10] = {P, a.jx, a.jy, a.jz, q_xx, q_yy, q_zz, q_xy, q_xz, q_yz};
+      auto emit = [&](auto nt) {
+        constexpr bool N = decltype(nt)::value;
+        store_out<N>((gptr<TP>)(sbase((gptr<char>)d_phi_g + static_cast<int64_t>(Z) * plane_bp) + lane_off(voff_p)),
+                     Enc<TP>::go(phin, 0.f, 1.f));
 #pragma unroll
-      for (int k = 0; k < NM; ++k)
-        store_out<NTS>((gptr<TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]));
+        for (int k = 0; k < NM; ++k)
+          store_out<N>((gptr<TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]));
+      };
+      if constexpr (NTS) {
+        if (b.whole_rows) emit(std::true_type{});
+        else emit(std::false_type{});
+      } else {
+        emit(std::false_type{});
+      }
     };
 
     for (int p = p_first; p <= p_last; ++p) {

@@ -36,7 +36,9 @@ struct BoxDesc {
   float enc_off[10];      // moment k stored as (v - off) * scale in 16-bit modes
   float enc_scale[10];
   float enc_inv[10];      // 1 / scale (exact: powers of two)
-  int32_t pad1[2];
+  int32_t whole_rows;     // 1 if every stored row starts on a 64-byte boundary
+                          // (row length and buffer bases multiples of 64 bytes)
+  int32_t pad1;
 };
 
 // One unit of work of the fused step: an output tile (x0, y0) of one box,
