@@ -90,7 +90,8 @@ enum {
 
 /* One box.  phi = 1 is the liquid (subscript l), phi = 0 the gas (g). */
 typedef struct {
-  int32_t nx, ny, nz;     /* >= 1; >= 2 on an axis with walls */
+  int32_t nx, ny, nz;     /* 1 .. 2^20; >= 2 on an axis with walls; nx rounded
+                             up to a multiple of 32, times ny, <= 2^28 */
   int32_t lattice;        /* lbm_lattice */
   int32_t bc[3];          /* lbm_bc per axis x, y, z */
   int32_t precision;      /* lbm_precision; identical for all boxes of a context */
@@ -144,7 +145,9 @@ typedef struct {
  * any device call.  The state is undefined until lbm_init_phase or
  * lbm_set_state has been called for every box.  On success *out owns all
  * device memory of the state (2 x 11 fields per box, ping-pong; 2 x 5 with
- * LBM_GRADIENT_CLOSURE). */
+ * LBM_GRADIENT_CLOSURE).  On the device each stored row of nx nodes is padded
+ * to a 64-byte multiple (at most 31 unused elements per row), so that every
+ * row of every field starts on a 64-byte boundary. */
 lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device* dev,
                       lbm_ctx** out);
 

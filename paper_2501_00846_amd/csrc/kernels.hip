@@ -333,14 +333,15 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     const BoxDesc& b = boxes[item.box];
     const int nx = b.nx, ny = b.ny, nz = b.nz;
     const int wx = b.wall[0], wy = b.wall[1], wz = b.wall[2];
-    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    const int pitch = b.pitch;
+    const int64_t plane = static_cast<int64_t>(pitch) * ny;
 
     const int x = item.x0 - 1 + tx;
     const int y = item.y0 - 1 + ty;
     int crx, cry;
     const int xm = map_axis(x, nx, wx, crx);
     const int ym = map_axis(y, ny, wy, cry);
-    const int64_t col = static_cast<int64_t>(ym) * nx + xm;
+    const int64_t col = static_cast<int64_t>(ym) * pitch + xm;
     const bool out_col = tx >= 1 && tx <= BX - 2 && ty >= 1 && ty <= BY - 2 && x < nx && y < ny;
     // per-lane flags kept in one VGPR; decoded where used inside the z loop
     // (bit 0/1: ghost column mirrored in x/y; bits 2-5: output node next to
@@ -382,7 +383,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     for (int j = 0; j < NPH; ++j) {
       const int e = tid + j * NT;
       const int i = e % PX, jj = e / PX;
-      phcol[j] = static_cast<uint32_t>(map_axis(item.y0 - 2 + jj, ny, wy) * nx + map_axis(item.x0 - 2 + i, nx, wx)) *
+      phcol[j] = static_cast<uint32_t>(map_axis(item.y0 - 2 + jj, ny, wy) * pitch + map_axis(item.x0 - 2 + i, nx, wx)) *
                  static_cast<uint32_t>(sizeof(TP));
     }
     // gradient closure: bit j set when halo element j lies across an odd
@@ -897,11 +898,20 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 // ---------------------------------------------------------------------------
 // Non-hot kernels: encode / decode / observables / diagnostics
 // ---------------------------------------------------------------------------
-// element of field f (0 = phi, 1..10 = moments) at node i of a box
-__device__ __forceinline__ int64_t mom_index(const BoxDesc& b, int k, int64_t i) {
-  const int64_t plane = static_cast<int64_t>(b.nx) * b.ny;
-  const int64_t z = i / plane;
-  return (z * b.nmom + k) * plane + (i - z * plane);
+// Storage offsets: rows are b.pitch elements apart.  Node (x, y, z) of phi,
+// and moment k of that node.
+__device__ __forceinline__ int64_t phi_at(const BoxDesc& b, int x, int y, int z) {
+  return (static_cast<int64_t>(z) * b.ny + y) * b.pitch + x;
+}
+__device__ __forceinline__ int64_t mom_at(const BoxDesc& b, int k, int x, int y, int z) {
+  return ((static_cast<int64_t>(z) * b.nmom + k) * b.ny + y) * b.pitch + x;
+}
+// coordinates of the flat node index i = x + nx (y + ny z)
+__device__ __forceinline__ void node_xyz(const BoxDesc& b, int64_t i, int& x, int& y, int& z) {
+  const int64_t r = i / b.nx;
+  x = static_cast<int>(i - r * b.nx);
+  y = static_cast<int>(r % b.ny);
+  z = static_cast<int>(r / b.ny);
 }
 
 template <class PR>
@@ -910,12 +920,14 @@ __global__ void encode_kernel(BoxDesc b, int parity, int field, const double* __
   using TP = typename PR::TP;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int x, y, z;
+    node_xyz(b, i, x, y, z);
     if (field == 0) {
-      ((gptr<TP>)b.phi[parity])[i] = Enc<TP>::go(src[i], 0.f, 1.f);
+      ((gptr<TP>)b.phi[parity])[phi_at(b, x, y, z)] = Enc<TP>::go(src[i], 0.f, 1.f);
     } else {
       const int k = field - 1;
       if (k < b.nmom)  // Q is not stored by the gradient closure
-        ((gptr<TM>)b.mom[parity])[mom_index(b, k, i)] = Enc<TM>::go(src[i], b.enc_off[k], b.enc_scale[k]);
+        ((gptr<TM>)b.mom[parity])[mom_at(b, k, x, y, z)] = Enc<TM>::go(src[i], b.enc_off[k], b.enc_scale[k]);
     }
   }
 }
@@ -926,11 +938,13 @@ __global__ void decode_kernel(BoxDesc b, int parity, int field, double* __restri
   using TP = typename PR::TP;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int x, y, z;
+    node_xyz(b, i, x, y, z);
     if (field == 0) {
-      dst[i] = dec<double>(((gptr<const TP>)b.phi[parity])[i], 0.f, 1.f);
+      dst[i] = dec<double>(((gptr<const TP>)b.phi[parity])[phi_at(b, x, y, z)], 0.f, 1.f);
     } else {
       const int k = field - 1;
-      dst[i] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_index(b, k, i)], b.enc_off[k], b.enc_inv[k])
+      dst[i] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_at(b, k, x, y, z)], b.enc_off[k], b.enc_inv[k])
                           : 0.0;
     }
   }
@@ -943,10 +957,11 @@ __global__ void gather_kernel(BoxDesc b, int parity, const int64_t* __restrict__
   using TP = typename PR::TP;
   for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < n;
        j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t i = idx[j];
-    out[j] = dec<double>(((gptr<const TP>)b.phi[parity])[i], 0.f, 1.f);
+    int x, y, z;
+    node_xyz(b, idx[j], x, y, z);
+    out[j] = dec<double>(((gptr<const TP>)b.phi[parity])[phi_at(b, x, y, z)], 0.f, 1.f);
     for (int k = 0; k < 10; ++k)
-      out[(k + 1) * n + j] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_index(b, k, i)],
+      out[(k + 1) * n + j] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_at(b, k, x, y, z)],
                                                       b.enc_off[k], b.enc_inv[k])
                                         : 0.0;
   }
@@ -960,17 +975,15 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
   using TM = typename PR::TM;
   using TP = typename PR::TP;
   const int nx = b.nx, ny = b.ny, nz = b.nz;
-  const int64_t plane = static_cast<int64_t>(nx) * ny;
   const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
   const gptr<const TM> fmom = (gptr<const TM>)b.mom[parity];
   double m[10];
-  const int64_t idx = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
   finite = true;
   for (int k = 0; k < 10; ++k) {
-    m[k] = k < b.nmom ? dec<double>(fmom[mom_index(b, k, idx)], b.enc_off[k], b.enc_inv[k]) : 0.0;
+    m[k] = k < b.nmom ? dec<double>(fmom[mom_at(b, k, x, y, z)], b.enc_off[k], b.enc_inv[k]) : 0.0;
     finite = finite && isfinite(m[k]);
   }
-  phi = dec<double>(fphi[idx], 0.f, 1.f);
+  phi = dec<double>(fphi[phi_at(b, x, y, z)], 0.f, 1.f);
   finite = finite && isfinite(phi);
   double g[3] = {0, 0, 0}, lap = 0;
   for (int cz = -1; cz <= 1; ++cz)
@@ -979,7 +992,7 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
         const int xx = map_axis(x + cx, nx, b.wall[0]);
         const int yy = map_axis(y + cy, ny, b.wall[1]);
         const int zz = map_axis(z + cz, nz, b.wall[2]);
-        const double v = dec<double>(fphi[static_cast<int64_t>(zz) * plane + static_cast<int64_t>(yy) * nx + xx], 0.f, 1.f);
+        const double v = dec<double>(fphi[phi_at(b, xx, yy, zz)], 0.f, 1.f);
         const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
         g[0] += 3.0 * w * cx * v;
         g[1] += 3.0 * w * cy * v;
@@ -1005,10 +1018,9 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
           const int yy = map_axis(y + cy, ny, b.wall[1], ky);
           const int zz = map_axis(z + cz, nz, b.wall[2], kz);
           const double sgn = ((kx + ky + kz) & 1) ? -1.0 : 1.0;
-          const int64_t id = static_cast<int64_t>(zz) * plane + static_cast<int64_t>(yy) * nx + xx;
           const double w = 3.0 * (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
           for (int a = 0; a < 3; ++a) {
-            const double ja = sgn * dec<double>(fmom[mom_index(b, 1 + a, id)], b.enc_off[1 + a], b.enc_inv[1 + a]);
+            const double ja = sgn * dec<double>(fmom[mom_at(b, 1 + a, xx, yy, zz)], b.enc_off[1 + a], b.enc_inv[1 + a]);
             gJ[a][0] += w * cx * ja;
             gJ[a][1] += w * cy * ja;
             gJ[a][2] += w * cz * ja;
@@ -1033,9 +1045,8 @@ __global__ void observable_kernel(BoxDesc b, int parity, int which, double* __re
   const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int x = static_cast<int>(i % b.nx);
-    const int y = static_cast<int>((i / b.nx) % b.ny);
-    const int z = static_cast<int>(i / (static_cast<int64_t>(b.nx) * b.ny));
+    int x, y, z;
+    node_xyz(b, i, x, y, z);
     double rho, u[3], phi, p, ps;
     bool fin;
     node_obs<PR>(b, parity, x, y, z, rho, u, phi, p, ps, fin);
@@ -1072,9 +1083,8 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(BoxDesc b, i
   const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int x = static_cast<int>(i % b.nx);
-    const int y = static_cast<int>((i / b.nx) % b.ny);
-    const int z = static_cast<int>(i / (static_cast<int64_t>(b.nx) * b.ny));
+    int x, y, z;
+    node_xyz(b, i, x, y, z);
     double rho, u[3], phi, p, ps;
     bool fin;
     node_obs<PR>(b, parity, x, y, z, rho, u, phi, p, ps, fin);
@@ -1192,6 +1202,11 @@ bool fused_config_supported(int precision, bool gc, int bx, int by) {
 }
 
 size_t phi_bytes(int precision, int64_t n) { return static_cast<size_t>(n) * (precision == kF64 ? 8 : 4); }
+int row_pitch(int precision, int nx) {
+  const int e = precision == kF64 ? 8 : (precision == kF32 ? 4 : 2);  // smaller of the phi and moment sizes
+  const int q = 64 / e;
+  return (nx + q - 1) / q * q;
+}
 size_t mom_bytes(int precision, int64_t n, int nmom) {
   const size_t e = precision == kF64 ? 8 : (precision == kF32 ? 4 : 2);
   return static_cast<size_t>(n) * static_cast<size_t>(nmom) * e;

@@ -15,8 +15,8 @@ constexpr int kFields = 11;  // phi, P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
 // uniform (scalar) loads by every workgroup working on the box.
 struct BoxDesc {
   // ping-pong state buffers, index = parity:
-  //   phi[s]: [nz][ny][nx] phase field (storage type of phi)
-  //   mom[s]: [nz][nmom][ny][nx] moments P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
+  //   phi[s]: [nz][ny][pitch] phase field (storage type of phi)
+  //   mom[s]: [nz][nmom][ny][pitch] moments P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
   //           (each z plane holds its nmom moment planes back to back;
   //           nmom = 4, P and J only, for the gradient closure)
   void* phi[2];
@@ -37,8 +37,9 @@ struct BoxDesc {
   float enc_scale[10];
   float enc_inv[10];      // 1 / scale (exact: powers of two)
   int32_t whole_rows;     // 1 if every stored row starts on a 64-byte boundary
-                          // (row length and buffer bases multiples of 64 bytes)
-  int32_t pad1;
+                          // (buffer bases multiples of 64 bytes)
+  int32_t pitch;          // elements from one stored row to the next (>= nx; the
+                          // padding after column nx-1 is never read or written)
 };
 
 // One unit of work of the fused step: an output tile (x0, y0) of one box,
@@ -63,6 +64,9 @@ int fused_blocks_per_cu(int precision, bool gc, int block_x, int block_y);
 // nmom moment fields.
 size_t phi_bytes(int precision, int64_t n);
 size_t mom_bytes(int precision, int64_t n, int nmom);
+// Stored row length (elements) for rows of nx nodes: nx rounded up so that
+// rows of phi and of every moment field start on 64-byte boundaries.
+int row_pitch(int precision, int nx);
 
 // Encode N doubles into field `field` (storage of `precision`).
 hipError_t launch_encode(int precision, const BoxDesc& box, int parity, int field,

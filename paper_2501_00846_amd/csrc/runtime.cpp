@@ -105,7 +105,8 @@ lbm_status validate_box(const lbm_params& p, int idx, int precision0) {
   if (p.lattice != LBM_D3Q27) return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: lattice %d unsupported (D3Q27 only)", who, idx, p.lattice);
   if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: dims must be >= 1", who, idx);
   if (p.nx > (1 << 20) || p.ny > (1 << 20) || p.nz > (1 << 20)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: dims must be <= 2^20", who, idx);
-  if (static_cast<int64_t>(p.nx) * p.ny > (int64_t(1) << 28)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: nx*ny must be <= 2^28", who, idx);
+  if (static_cast<int64_t>(lbm::row_pitch(LBM_BF16_OS, p.nx)) * p.ny > (int64_t(1) << 28))
+    return fail(nullptr, LBM_ERR_ARG, "%s: box %d: nx (rounded up to a multiple of 32) * ny must be <= 2^28", who, idx);
   const int d[3] = {p.nx, p.ny, p.nz};
   for (int a = 0; a < 3; ++a) {
     if (p.bc[a] != LBM_PERIODIC && p.bc[a] != LBM_WALL) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: bc[%d] = %d invalid", who, idx, a, p.bc[a]);
@@ -142,8 +143,8 @@ void fill_desc(Box& b, int precision) {
   d.kappa_ac = 4.0 * p.mobility / p.width;
   for (int a = 0; a < 3; ++a) d.grav[a] = p.gravity[a];
   d.rho_ref = p.rho_ref;
-  bool rows = (static_cast<size_t>(p.nx) * lbm::phi_bytes(precision, 1)) % 64 == 0 &&
-              (static_cast<size_t>(p.nx) * lbm::mom_bytes(precision, 1, 1)) % 64 == 0;
+  d.pitch = lbm::row_pitch(precision, p.nx);
+  bool rows = true;  // rows of pitch elements are whole 64-byte multiples
   for (int s = 0; s < 2; ++s)
     rows = rows && reinterpret_cast<uintptr_t>(d.phi[s]) % 64 == 0 && reinterpret_cast<uintptr_t>(d.mom[s]) % 64 == 0;
   d.whole_rows = rows ? 1 : 0;
@@ -356,8 +357,10 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
       b.prm = boxes[i];
       b.n = static_cast<int64_t>(b.prm.nx) * b.prm.ny * b.prm.nz;
       default_encoding(b);
-      const size_t pb = align256(lbm::phi_bytes(c->precision, b.n));
-      const size_t total = pb + align256(lbm::mom_bytes(c->precision, b.n, nmom_of(b.prm)));
+      // stored rows are padded to row_pitch elements (64-byte aligned rows)
+      const int64_t stored = static_cast<int64_t>(lbm::row_pitch(c->precision, b.prm.nx)) * b.prm.ny * b.prm.nz;
+      const size_t pb = align256(lbm::phi_bytes(c->precision, stored));
+      const size_t total = pb + align256(lbm::mom_bytes(c->precision, stored, nmom_of(b.prm)));
       for (int s = 0; s < 2; ++s) {
         b.mem[s] = dev_alloc(c, total);
         if (!b.mem[s]) {
