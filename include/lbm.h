@@ -196,8 +196,9 @@ lbm_status lbm_set_tuning(lbm_ctx* ctx, const lbm_tuning* t);
 lbm_status lbm_get_tuning(const lbm_ctx* ctx, lbm_tuning* t);
 
 /* Time each supported tuning for `steps` steps (each after two warm-up
- * steps), time the finalists within 5 % of the fastest twice more over
- * 2*steps steps, and keep the tuning with the best time per step.  Advances
+ * steps), time the finalists within 5 % of the fastest twice more (over
+ * 2*steps steps, or enough steps to span ~25 ms, at most 4096), and keep the
+ * tuning with the best time per step.  Advances
  * the state by every step it runs.  Writes the choice to *best if non-NULL.
  * On an error the previous tuning stays in place. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps, lbm_tuning* best);
