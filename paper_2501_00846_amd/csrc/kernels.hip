@@ -907,7 +907,17 @@ __device__ __forceinline__ int64_t mom_at(const BoxDesc& b, int k, int x, int y,
   return ((static_cast<int64_t>(z) * b.nmom + k) * b.ny + y) * b.pitch + x;
 }
 // coordinates of the flat node index i = x + nx (y + ny z)
+// (32-bit divisions whenever the index fits, which covers boxes of up to
+// 2^32 nodes; 64-bit ones beyond)
 __device__ __forceinline__ void node_xyz(const BoxDesc& b, int64_t i, int& x, int& y, int& z) {
+  if (static_cast<uint64_t>(i) <= 0xffffffffull) {
+    const uint32_t ii = static_cast<uint32_t>(i), unx = static_cast<uint32_t>(b.nx), uny = static_cast<uint32_t>(b.ny);
+    const uint32_t r = ii / unx;
+    x = static_cast<int>(ii - r * unx);
+    y = static_cast<int>(r % uny);
+    z = static_cast<int>(r / uny);
+    return;
+  }
   const int64_t r = i / b.nx;
   x = static_cast<int>(i - r * b.nx);
   y = static_cast<int>(r % b.ny);
@@ -985,20 +995,27 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
   }
   phi = dec<double>(fphi[phi_at(b, x, y, z)], 0.f, 1.f);
   finite = finite && isfinite(phi);
+  // neighbour coordinates per axis (wrap or mirror) and wall-crossing flags,
+  // resolved once: xs[c + 1], ks_x[c + 1] for c = -1, 0, 1
+  int xs[3], ys[3], zs[3], kxs[3], kys[3], kzs[3];
+  for (int c = -1; c <= 1; ++c) {
+    xs[c + 1] = map_axis(x + c, nx, b.wall[0], kxs[c + 1]);
+    ys[c + 1] = map_axis(y + c, ny, b.wall[1], kys[c + 1]);
+    zs[c + 1] = map_axis(z + c, nz, b.wall[2], kzs[c + 1]);
+  }
   double g[3] = {0, 0, 0}, lap = 0;
   for (int cz = -1; cz <= 1; ++cz)
-    for (int cy = -1; cy <= 1; ++cy)
+    for (int cy = -1; cy <= 1; ++cy) {
+      const gptr<const TP> row = fphi + phi_at(b, 0, ys[cy + 1], zs[cz + 1]);
       for (int cx = -1; cx <= 1; ++cx) {
-        const int xx = map_axis(x + cx, nx, b.wall[0]);
-        const int yy = map_axis(y + cy, ny, b.wall[1]);
-        const int zz = map_axis(z + cz, nz, b.wall[2]);
-        const double v = dec<double>(fphi[phi_at(b, xx, yy, zz)], 0.f, 1.f);
+        const double v = dec<double>(row[xs[cx + 1]], 0.f, 1.f);
         const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
         g[0] += 3.0 * w * cx * v;
         g[1] += 3.0 * w * cy * v;
         g[2] += 3.0 * w * cz * v;
         lap += 6.0 * w * (v - phi);
       }
+    }
   const double phic = fmin(fmax(phi, 0.0), 1.0);
   rho = b.rho_g + phic * b.drho;
   const double nu = b.nu_g + phic * b.dnu;
@@ -1010,22 +1027,21 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
     // gradient closure: the viscous correction contracts -(cs^2/omega)(grad J + grad J^T),
     // J ghosts minus the mirrored value per wall crossed
     double gJ[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const int64_t fstride = static_cast<int64_t>(ny) * b.pitch;  // one moment plane
     for (int cz = -1; cz <= 1; ++cz)
-      for (int cy = -1; cy <= 1; ++cy)
+      for (int cy = -1; cy <= 1; ++cy) {
+        const gptr<const TM> rowJ = fmom + mom_at(b, 1, 0, ys[cy + 1], zs[cz + 1]);
         for (int cx = -1; cx <= 1; ++cx) {
-          int kx, ky, kz;
-          const int xx = map_axis(x + cx, nx, b.wall[0], kx);
-          const int yy = map_axis(y + cy, ny, b.wall[1], ky);
-          const int zz = map_axis(z + cz, nz, b.wall[2], kz);
-          const double sgn = ((kx + ky + kz) & 1) ? -1.0 : 1.0;
+          const double sgn = ((kxs[cx + 1] + kys[cy + 1] + kzs[cz + 1]) & 1) ? -1.0 : 1.0;
           const double w = 3.0 * (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
           for (int a = 0; a < 3; ++a) {
-            const double ja = sgn * dec<double>(fmom[mom_at(b, 1 + a, xx, yy, zz)], b.enc_off[1 + a], b.enc_inv[1 + a]);
+            const double ja = sgn * dec<double>(rowJ[a * fstride + xs[cx + 1]], b.enc_off[1 + a], b.enc_inv[1 + a]);
             gJ[a][0] += w * cx * ja;
             gJ[a][1] += w * cy * ja;
             gJ[a][2] += w * cz * ja;
           }
         }
+      }
     for (int a = 0; a < 3; ++a)
       for (int c = 0; c < 3; ++c) Q[a][c] = -(1.0 / 3.0) / om * (gJ[a][c] + gJ[c][a]);
   }
