@@ -1057,7 +1057,7 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
 }
 
 template <class PR>
-__global__ void observable_kernel(BoxDesc b, int parity, int which, double* __restrict__ dst) {
+__global__ void __launch_bounds__(256) observable_kernel(BoxDesc b, int parity, int which, double* __restrict__ dst) {
   const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -1122,7 +1122,9 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(BoxDesc b, i
     if (phi <= 0.02) { acc[22] += p; acc[23] += 1.0; }
     if (!fin) acc[24] = 1.0;
   }
-  // block reduction, fixed order
+  // block reduction, fixed order (unrolled: a runtime index into acc would
+  // move the accumulators from registers to scratch memory)
+#pragma unroll
   for (int k = 0; k < kDiagValues; ++k) {
     red[threadIdx.x] = acc[k];
     __syncthreads();
