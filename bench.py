@@ -131,17 +131,24 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None
     step = ctx.step_unbatched if unbatched else ctx.step
     step(warmup)
     ctx.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # the timed steps run as five consecutive segments with HIP events on the
+    # library's stream between them (no synchronisation inside the region):
+    # the per-step kernel time is the whole region's, and the five segment
+    # times give its median and spread
+    nseg = 5 if steps >= 5 else 1
+    bounds = [steps * i // nseg for i in range(nseg + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nseg + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(ctx.stream)
-    step(steps)
-    e1.record(ctx.stream)
+    ev[0].record(ctx.stream)
+    for i in range(nseg):
+        step(bounds[i + 1] - bounds[i])
+        ev[i + 1].record(ctx.stream)
     ctx.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = e0.elapsed_time(e1) / steps
+    kern_ms = ev[0].elapsed_time(ev[nseg]) / steps
+    seg_ms = [ev[i].elapsed_time(ev[i + 1]) / (bounds[i + 1] - bounds[i]) for i in range(nseg)]
     nodes = ctx.total_nodes
     bpl = ctx.bytes_per_update
     diag = ctx.diagnostics(0)
@@ -149,7 +156,9 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None
     ctx.close()
     mlups = nodes * steps / wall / 1e6
     achieved = nodes * bpl / (kern_ms * 1e-3) / 1e9
-    return dict(mlups=mlups, ms_per_step=wall / steps * 1e3, kernel_ms=kern_ms, nodes=nodes,
+    return dict(mlups=mlups, ms_per_step=wall / steps * 1e3, kernel_ms=kern_ms,
+                kernel_ms_segments=[round(v, 5) for v in seg_ms],
+                kernel_ms_median=float(np.median(seg_ms)), nodes=nodes,
                 bytes_per_update=bpl, achieved_gbs=achieved, frac=achieved / PEAK_HBM_GBS,
                 tuning=tuning, phase_mass=diag["phase_mass"], nonfinite=diag["nonfinite"])
 
@@ -456,6 +465,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "modes": {p: {"mlups": round(v["mlups"], 1), "kernel_ms": round(v["kernel_ms"], 4),
+                      "kernel_ms_median_of_5": round(v["kernel_ms_median"], 4),
+                      "kernel_ms_segments": v["kernel_ms_segments"],
                       "achieved_gbs": round(v["achieved_gbs"], 1), "frac": round(v["frac"], 4),
                       "bytes_per_update": v["bytes_per_update"], "tuning": v["tuning"],
                       "nonfinite": v["nonfinite"]} for p, v in modes.items()},

@@ -189,7 +189,7 @@ lbm_status upload_boxes(lbm_ctx* c) {
 lbm_status build_items(lbm_ctx* c) {
   const int tx = c->tuning.block_x - 2, ty = c->tuning.block_y - 2;
   std::vector<Item> all;
-  c->box_items.clear();
+  std::vector<std::pair<int, int>> box_items;
   for (size_t bi = 0; bi < c->boxes.size(); ++bi) {
     const lbm_params& p = c->boxes[bi].prm;
     const int zc = std::max(1, std::min(c->tuning.z_chunk, p.nz));
@@ -205,7 +205,7 @@ lbm_status build_items(lbm_ctx* c) {
           it.z1 = std::min(z0 + zc, p.nz);
           items.push_back(it);
         }
-    c->box_items.emplace_back(static_cast<int>(all.size()), static_cast<int>(items.size()));
+    box_items.emplace_back(static_cast<int>(all.size()), static_cast<int>(items.size()));
     // XCD-contiguous permutation within the box
     const size_t n = items.size();
     const size_t per = (n + 7) / 8;
@@ -221,12 +221,20 @@ lbm_status build_items(lbm_ctx* c) {
     }
     all.insert(all.end(), perm.begin(), perm.end());
   }
+  // the new list replaces the old one only once it is on the device, so a
+  // failure leaves the context on its previous, consistent tile list
+  Item* d_new = static_cast<Item*>(dev_alloc(c, align256(all.size() * sizeof(Item))));
+  if (!d_new) return fail(c, LBM_ERR_OOM, "tile list allocation failed");
+  hipError_t e = hipMemcpyAsync(d_new, all.data(), all.size() * sizeof(Item), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    dev_free(c, d_new);
+    return fail(c, LBM_ERR_DEVICE, "tile list upload failed: %s", hipGetErrorString(e));
+  }
   if (c->d_items) dev_free(c, c->d_items);
-  c->d_items = static_cast<Item*>(dev_alloc(c, align256(all.size() * sizeof(Item))));
-  if (!c->d_items) return fail(c, LBM_ERR_OOM, "tile list allocation failed");
-  HIP_TRY(c, hipMemcpyAsync(c->d_items, all.data(), all.size() * sizeof(Item), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->d_items = d_new;
   c->n_items = static_cast<int>(all.size());
+  c->box_items = std::move(box_items);
   drop_graphs(c);
   return LBM_OK;
 }
@@ -585,8 +593,11 @@ lbm_status lbm_set_tuning(lbm_ctx* c, const lbm_tuning* t) {
   if (t->z_chunk < 1) return fail(c, LBM_ERR_ARG, "lbm_set_tuning: z_chunk must be >= 1");
   if (t->persistent < 0) return fail(c, LBM_ERR_ARG, "lbm_set_tuning: persistent must be >= 0");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const lbm_tuning before = c->tuning;
   c->tuning = *t;
-  return build_items(c);
+  lbm_status s = build_items(c);
+  if (s != LBM_OK) c->tuning = before;  // the previous tile list is still in place
+  return s;
 }
 
 lbm_status lbm_get_tuning(const lbm_ctx* c, lbm_tuning* t) {
