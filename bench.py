@@ -255,7 +255,11 @@ def precision_study(args):
         "C2": (WL.rising_bubble(), 20000, 500, "ucom"),
         "C3": (WL.droplet_collision(), 5000, 500, None),
     }
-    out = {}
+    if args.closure == "gradient":
+        # every mode, FP64 included, runs the gradient closure
+        for case, _, _, _ in studies.values():
+            case.problem.gradient_closure = True
+    out = {"closure": args.closure}
     for name, (case, steps, every, extra) in studies.items():
         log("precision study %s: %d steps" % (name, steps))
         ref, rtrace, rfail = _fields_and_diag(case, "fp64", steps, every)
