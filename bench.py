@@ -71,11 +71,14 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(config, precision, tuning):
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(config, precision, tuning, path=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source at the same tile shape and z-chunk;
     else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or TRAFFIC_JSON
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -345,7 +348,7 @@ def summarize_counters(args):
     f_fetch = COPY_BYTES / (cf * 1024.0)
     f_write = COPY_BYTES / (cw * 1024.0)
     traffic = fetch * 1024.0 * f_fetch + write * 1024.0 * f_write
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = getattr(args, "traffic_json", None) or TRAFFIC_JSON
     data = json.load(open(path)) if os.path.exists(path) else {}
     cases, _ = make_cases(args.config)
     nodes = sum(c.problem.n_nodes for c in cases)

@@ -1,0 +1,90 @@
+"""Host logic of bench.py (no GPU): the measured-traffic table and its lookup,
+and the refusal of multi-GPU runs."""
+import argparse
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _counter_csv(path, counter, rows):
+    """rows: (dispatch id, kernel name, value) -> a rocprofv3-style
+    counter_collection.csv (one row per dispatch and hardware instance)."""
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, k, v in rows:
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_traffic_key_names_workload_precision_and_launch():
+    assert bench.traffic_key("C2", "fp64", [34, 15, 43, 0]) == "C2/fp64@34,15,43"
+    assert bench.traffic_key("C5/gc", "fp32", [34, 15, 128]) == "C5/gc/fp32@34,15,128"
+
+
+def test_counter_summary_scaling_and_lookup(tmp_path):
+    """Counters of two dispatches (each split over two hardware instances) are
+    averaged per dispatch and scaled by the copy calibration: the copy moves
+    COPY_BYTES each way, FETCH_SIZE reports 2/5 of it and WRITE_SIZE all of it,
+    so reads scale by 2.5 and writes by 1."""
+    kib = bench.COPY_BYTES / 1024.0
+    fetch = tmp_path / "fetch.csv"
+    write = tmp_path / "write.csv"
+    cfetch = tmp_path / "cfetch.csv"
+    cwrite = tmp_path / "cwrite.csv"
+    k = "void lbm::fused_step<34, 15, PF64, false>(...)"
+    _counter_csv(fetch, "FETCH_SIZE", [(1, k, 300.0), (1, k, 100.0), (2, k, 200.0), (2, k, 200.0),
+                                       (3, "encode_kernel", 9e9)])
+    _counter_csv(write, "WRITE_SIZE", [(1, k, 500.0), (2, k, 700.0)])
+    _counter_csv(cfetch, "FETCH_SIZE", [(7, "elementwise_kernel", 0.4 * kib)])
+    _counter_csv(cwrite, "WRITE_SIZE", [(7, "elementwise_kernel", kib)])
+    out = tmp_path / "traffic.json"
+    args = argparse.Namespace(fetch_csv=str(fetch), write_csv=str(write), copy_fetch_csv=str(cfetch),
+                              copy_write_csv=str(cwrite), copy_kernel="elementwise", config="C1",
+                              precision="fp64", closure="moment", tuning="18,14,8,0",
+                              traffic_json=str(out))
+    bench.summarize_counters(args)
+    data = json.load(open(out))
+    ent = data["C1/fp64@18,14,8"]
+    assert abs(ent["fetch_scale"] - 2.5) < 1e-12 and ent["write_scale"] == 1.0
+    expect = 400.0 * 1024 * 2.5 + 600.0 * 1024
+    assert abs(ent["bytes_per_launch"] - expect) < 1e-6
+    assert ent["bytes_per_update_algorithmic"] == 176
+    assert abs(ent["bytes_per_update_measured"] - expect / 32768) < 1e-9
+    # reported only for the same launch on the same kernel source
+    tuning = {"block_x": 18, "block_y": 14, "z_chunk": 8}
+    assert bench.measured_traffic("C1", "fp64", tuning, path=str(out)) == ent["bytes_per_launch"]
+    assert bench.measured_traffic("C1", "fp64", dict(tuning, z_chunk=16), path=str(out)) is None
+    assert bench.measured_traffic("C1", "fp32", tuning, path=str(out)) is None
+    data["C1/fp64@18,14,8"]["kernel_hash"] = "0" * 16
+    json.dump(data, open(out, "w"))
+    assert bench.measured_traffic("C1", "fp64", tuning, path=str(out)) is None
+
+
+def test_committed_traffic_entries_are_well_formed():
+    """profiles/traffic.json: every entry names its launch in its key and
+    holds positive, consistent byte counts.  Entries taken on an older kernel
+    source are kept but not reported (bench.py reports traffic as null)."""
+    data = json.load(open(bench.TRAFFIC_JSON))
+    assert data
+    for key, ent in data.items():
+        config, rest = key.rsplit("/", 1)
+        prec, launch = rest.split("@")
+        assert key == bench.traffic_key(config, prec, ent["tuning"]), key
+        assert ent["bytes_per_launch"] > 0 and ent["nodes"] > 0
+        assert abs(ent["bytes_per_update_measured"] * ent["nodes"] - ent["bytes_per_launch"]) < 1e-3 * ent["bytes_per_launch"]
+        # measured traffic cannot undercut the algorithmic minimum
+        assert ent["bytes_per_update_measured"] >= ent["bytes_per_update_algorithmic"], key
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
