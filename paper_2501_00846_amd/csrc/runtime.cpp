@@ -621,7 +621,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
   int maxz = 1;
   for (auto& b : c->boxes) maxz = std::max(maxz, b.prm.nz);
   std::vector<int> fixed_zcs;
-  for (int z : {8, 16, 32, 64, 128})
+  for (int z : {2, 4, 8, 16, 32, 64, 128})
     if (z <= maxz) fixed_zcs.push_back(z);
   if (fixed_zcs.empty() || fixed_zcs.back() < maxz) fixed_zcs.push_back(maxz);
   int dev = 0, cus = 0;
@@ -643,7 +643,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
     const int slots = cus * lbm::fused_blocks_per_cu(c->precision, c->gc, sh[0], sh[1]);
     for (int rounds = 1; slots > 0 && rounds <= 4; ++rounds) {
       const int zc = wave_balanced_chunk(c, sh[0] - 2, sh[1] - 2, static_cast<int64_t>(rounds) * slots, maxz);
-      if (zc >= 4 && std::find(zcs.begin(), zcs.end(), zc) == zcs.end()) zcs.push_back(zc);
+      if (zc >= 2 && std::find(zcs.begin(), zcs.end(), zc) == zcs.end()) zcs.push_back(zc);
     }
     for (int zc : zcs) cands.push_back({lbm_tuning{sh[0], sh[1], zc, 0}, 1e30f});
   }
