@@ -101,3 +101,12 @@ def test_python_binding_raises_lbm_error():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.lbm_create([_params(nx=0)])
     assert ei.value.status == -1
+
+
+def test_create_rejects_oversized_boxes():
+    """Edges are at most 2^20, and a stored plane (rows padded to a multiple of
+    32 elements) at most 2^28 elements, so per-lane byte offsets stay 32-bit."""
+    st, _, msg = _create([_params(nx=(1 << 20) + 1)])
+    assert st == -1 and "2^20" in msg
+    st, _, msg = _create([_params(nx=16385, ny=16384, nz=1)])
+    assert st == -1 and "2^28" in msg

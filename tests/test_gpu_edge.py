@@ -1,0 +1,77 @@
+"""Edge cases of the fused step on the GPU: zero steps, single-phase boxes
+(no interface, so the phase-field normal takes its guarded zero-gradient
+value), and the longest column the library accepts."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2501_00846_amd import lbm
+from paper_2501_00846_amd.workloads import PERIODIC, WALL, Problem
+from tests.gpu_util import gpu_run_state, oracle_run_state, rel_err, smooth_random_state
+
+pytestmark = pytest.mark.gpu
+
+P_, W_ = PERIODIC, WALL
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_zero_steps_leave_the_state_unchanged():
+    prob = Problem(37, 29, 23, bc=(P_, W_, P_), rho_l=1.0, rho_g=0.01, nu_l=0.02, nu_g=0.1, sigma=0.01)
+    state = smooth_random_state(prob, seed=21)
+    with lbm.Context(prob, "fp64") as ctx:
+        ctx.set_state(0, state.reshape(-1))
+        ctx.step(0)
+        got = ctx.get_state(0)
+    assert np.array_equal(got, state)
+
+
+@pytest.mark.parametrize("phi0", [1.0, 0.0])
+@pytest.mark.parametrize("bc", [(P_, P_, P_), (W_, P_, W_)])
+def test_single_phase_box_fp64(phi0, bc):
+    """phi = 1 (liquid) or phi = 0 (gas, density 1/1000 of the liquid)
+    everywhere, with a random flow: grad phi = 0 at every node at the start,
+    so the interface normal takes the guarded value on both sides.  (phi = 0
+    stays exactly 0; phi = 1 follows 1 - div u, since the advection is in flux
+    form.)  20 steps, FP64 GPU against the oracle."""
+    prob = Problem(33, 14, 11, bc=bc, rho_l=1.0, rho_g=1e-3, nu_l=1 / 60, nu_g=1 / 6, sigma=0.01,
+                   gravity=(0.0, 0.0, -1e-6), rho_ref=1.0)
+    state = smooth_random_state(prob, seed=31, amp_u=0.01)
+    state[0] = phi0
+    _log("single phase phi=%g bc=%s" % (phi0, bc))
+    got = gpu_run_state(prob, state, 20)
+    ref = oracle_run_state(prob, state, 20)
+    if phi0 == 0.0:
+        assert not np.any(ref[0]) and not np.any(got[0]), "phi = 0 must stay exactly 0"
+        got, ref = got[1:], ref[1:]
+        err = {k: float(np.abs(got[i] - ref[i]).max() / np.abs(ref[i]).max()) for i, k in enumerate(lbm.FIELDS[1:])}
+    else:
+        err = rel_err(got, ref)
+    assert max(err.values()) <= 1e-11, err
+
+
+def test_longest_column_fp64():
+    """A 1 x 1 x 2^20 periodic column, the longest edge accepted: one step
+    against the oracle."""
+    n = 1 << 20
+    prob = Problem(1, 1, n, bc=(P_, P_, P_), rho_l=1.0, rho_g=0.01, nu_l=0.02, nu_g=0.1, sigma=0.01,
+                   gravity=(0.0, 0.0, 1e-6), rho_ref=0.5)
+    z = np.arange(n, dtype=np.float64)
+    state = np.zeros((11, n, 1, 1))
+    state[0, :, 0, 0] = 0.5 + 0.45 * np.sin(2 * np.pi * 8 * z / n)
+    state[4, :, 0, 0] = 1e-3 * np.cos(2 * np.pi * 3 * z / n)  # J_z
+    _log("column 1x1x%d fp64" % n)
+    got = gpu_run_state(prob, state, 1)
+    ref = oracle_run_state(prob, state, 1)
+    # P starts at zero and the x, y moments of this z-only flow are round-off:
+    # each moment is a signed sum of populations of size max(|P|, |J|), so
+    # agreement is judged on that scale
+    s_mom = max(np.abs(ref[1]).max(), np.abs(ref[2:5]).max())
+    for k, name in enumerate(lbm.FIELDS):
+        scale = np.abs(ref[k]).max() if k == 0 else max(np.abs(ref[k]).max(), s_mom)
+        err = np.abs(got[k] - ref[k]).max()
+        assert err <= 1e-12 * scale, (name, err, scale)
