@@ -374,7 +374,8 @@ def summarize_counters(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's own run length, 400 for the second workloads)")
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C4", "C5", "raindrop", "eoga"])
     ap.add_argument("--precision", default=None,
@@ -417,6 +418,9 @@ def main():
 
     defaults = {"C1": "fp64", "C2": "fp64,fp32", "C3": "fp32,fp16_os,bf16_os", "C4": "fp32",
                 "C5": "fp32,fp16_os,fp64", "raindrop": "fp32", "eoga": "fp32"}
+    if args.steps is None:
+        # each workload is timed over its own run length
+        args.steps = {"C1": 500, "C2": 20000, "C3": 5000, "C4": 2000, "C5": 2000}.get(args.config, 400)
     precisions = (args.precision or defaults[args.config]).split(",")
     log("bench: building cases for %s" % args.config)
     cases, desc = make_cases(args.config)
