@@ -417,11 +417,6 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         if (j < NPH - 1 || e < PX * PY) sh.phi[e] = v[j];
       }
     };
-    auto stage_phi = [&](int q) {
-      R v[NPH];
-      load_phi(q, v);
-      store_phi(v);
-    };
     // returns (A', Bx', By', phi_c): A' = s_x s_y phi, Bx' = s_y d_x phi,
     // By' = s_x d_y phi with s = (1,4,1), d = (-1,0,1)
     auto filter_phi = [&](R* F) {
@@ -488,24 +483,6 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     R Fm[4], F0[4], Fp[4];
     R JFm[GC ? 3 : 1][4], JF0[GC ? 3 : 1][4], JFp[GC ? 3 : 1][4];
     R jnxt[GC ? 3 : 1][NPH];
-    stage_phi(p_first - 1);
-    if constexpr (GC) {
-      load_J(p_first - 1, jnxt);
-      store_J(jnxt, p_first - 1);
-    }
-    __syncthreads();
-    filter_phi(Fm);
-    if constexpr (GC) filter_J(JFm);
-    __syncthreads();
-    stage_phi(p_first);
-    if constexpr (GC) {
-      load_J(p_first, jnxt);
-      store_J(jnxt, p_first);
-    }
-    __syncthreads();
-    filter_phi(F0);
-    if constexpr (GC) filter_J(JF0);
-    __syncthreads();
 
     // moments of the own column, prefetched one plane ahead
     R nxt[NL];
@@ -515,10 +492,34 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       for (int k = 0; k < NL; ++k)
         m[k] = dec<R>(*(gptr<const TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), b.enc_off[k], b.enc_inv[k]);
     };
+
+    // The two planes staged before the march and the first prefetch are all
+    // requested before any of them is used: an item then waits for memory
+    // once up front instead of three times in a row (the in-order counter
+    // lets each use wait only for the loads issued before it).
+    R ph0[NPH], ph1[NPH];
+    R jq0[GC ? 3 : 1][NPH], jq1[GC ? 3 : 1][NPH];
+    load_phi(p_first - 1, ph0);
+    if constexpr (GC) load_J(p_first - 1, jq0);
+    load_phi(p_first, ph1);
+    if constexpr (GC) load_J(p_first, jq1);
     load_moments(p_first, nxt);
     R phinxt[NPH];
     load_phi(p_first + 1, phinxt);
     if constexpr (GC) load_J(p_first + 1, jnxt);
+
+    store_phi(ph0);
+    if constexpr (GC) store_J(jq0, p_first - 1);
+    __syncthreads();
+    filter_phi(Fm);
+    if constexpr (GC) filter_J(JFm);
+    __syncthreads();
+    store_phi(ph1);
+    if constexpr (GC) store_J(jq1, p_first);
+    __syncthreads();
+    filter_phi(F0);
+    if constexpr (GC) filter_J(JF0);
+    __syncthreads();
 
     // Prefetched registers are consumed here, before this plane's global
     // stores are issued: loads and stores retire through one in-order vector
