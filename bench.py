@@ -3,19 +3,25 @@
 One step = one pass of the whole fused update over every node of the
 workload.  Prints ONE JSON line:
   value        MLUPS (million lattice updates per second) of the headline
-               precision, wall clock over K steps with inputs resident in HBM
+               precision (the first of --precision), wall clock over K steps
+               with inputs resident in HBM
   roofline     achieved HBM GB/s of the fused kernel from its algorithmic bytes
                (11 state fields read + 11 written per node) over the kernel
-               time measured with HIP events on the library's stream
+               time measured with HIP events on the library's stream, and the
+               vector-ALU ceiling beside it (committed SQ_INSTS_VALU count
+               over the issue rate of the 256 CUs)
   cpu_baseline the FP64 CPU oracle timed on this host on a bounded sample
-  modes        the same figures for every storage precision that was run
+  modes        the same figures for every storage precision that was run,
+               each with its per-field error against the FP64 run of the same
+               step count (phi, rho, u, p; relative L2 and max norms)
 
 Workloads (seeded, synthetic; lattice units):
   C1  static droplet 32^3, periodic
-  C2  rising bubble 128 x 128 x 256, no-slip walls on all faces (default)
+  C2  rising bubble 128 x 128 x 256, no-slip walls on all faces
   C3  binary droplet collision 256^3, periodic
   C4  ensemble of 64 periodic boxes with edges in [24, 96]
-  C5  drop falling into a pool 512^3, walls on +-z
+  C5  drop falling into a pool 512^3, walls on +-z (default: the largest
+      single-domain workload, FP64 headline with FP32 and FP16-os storage)
 """
 import argparse
 import hashlib
@@ -30,6 +36,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# vector-ALU issue ceiling in wave64 instructions per second: 256 CUs x 4 SIMDs
+# at 2.4 GHz, each SIMD (16 lanes) retiring one wave64 instruction per 4
+# cycles (FP64 and unpacked FP32 alike; packed FP32 is not used)
+CUS, SIMDS, CLOCK_HZ = 256, 4, 2.4e9
+VALU_ISSUE_PER_S = CUS * SIMDS * CLOCK_HZ / 4.0
 PAPER_CONTEXT = {"glups": 1.49, "hardware": "1x NVIDIA A100 64GB", "workload": "512^3 two-phase, water-air",
                  "precision": "not stated"}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16_os": "f32 (fp16 offset-scale storage)",
@@ -119,7 +130,74 @@ def copy_bandwidth(nbytes=1 << 31, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None):
+VALU_JSON = os.path.join(ROOT, "profiles", "valu.json")
+
+
+def wave_planes(problems, tuning):
+    """Wave64-planes one launch of the fused step executes: every item (a tile
+    of (block_x - 2) x (block_y - 2) output columns over z_chunk output planes)
+    marches its output planes plus one staging plane on each side that is not
+    a z wall, with ceil(block_x * block_y / 64) wavefronts.  Mirrors the tile
+    list of the runtime and the plane loop of the kernel."""
+    bx, by, zc0 = (int(tuning[k]) for k in ("block_x", "block_y", "z_chunk"))
+    tx, ty = bx - 2, by - 2
+    waves = -(-bx * by // 64)
+    total = 0
+    for p in problems:
+        wz = p.bc[2] == 1
+        zc = max(1, min(zc0, p.nz))
+        cols = -(-p.nx // tx) * -(-p.ny // ty)
+        planes = 0
+        for z0 in range(0, p.nz, zc):
+            z1 = min(z0 + zc, p.nz)
+            first = 0 if (wz and z0 == 0) else z0 - 1
+            last = p.nz - 1 if (wz and z1 == p.nz) else z1
+            planes += last - first + 1
+        total += cols * planes * waves
+    return total
+
+
+def valu_key(config, precision, tuning):
+    """Entry name in profiles/valu.json: workload (with "/gc" for the gradient
+    closure), precision and tile shape."""
+    return "%s/%s@%d,%d" % (config, precision, int(tuning["block_x"]), int(tuning["block_y"]))
+
+
+def valu_per_launch(config, precision, problems, tuning, path=None):
+    """Vector-ALU wave instructions of one launch: the committed SQ_INSTS_VALU
+    count per wave-plane (same kernel source and tile shape) times the
+    wave-planes of this launch; None when no such count is committed."""
+    path = path or VALU_JSON
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(valu_key(config, precision, tuning))
+    if not ent or ent.get("kernel_hash") != kernel_hash():
+        return None
+    return ent["valu_per_wave_plane"] * wave_planes(problems, tuning)
+
+
+def alu_ceiling(valu, nodes, kernel_ms):
+    """The vector-ALU floor of a launch of `valu` wave instructions at the
+    issue rate VALU_ISSUE_PER_S, as time, MLUPS and the fraction of the
+    measured kernel time it accounts for."""
+    if valu is None:
+        return None
+    floor_ms = valu / VALU_ISSUE_PER_S * 1e3
+    return {"valu_per_launch": int(round(valu)), "valu_per_update": round(valu * 64 / nodes, 1),
+            "issue_peak_ginst_s": round(VALU_ISSUE_PER_S / 1e9, 1), "floor_ms": round(floor_ms, 4),
+            "ceiling_mlups": round(nodes / (floor_ms * 1e-3) / 1e6, 1),
+            "achieved_ginst_s": round(valu / (kernel_ms * 1e-3) / 1e9, 1),
+            "frac": round(floor_ms / kernel_ms, 4)}
+
+
+def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None, fields=False):
+    """Autotune (or take `tuning`), restart from the initial fields, run
+    `warmup` steps, time `steps` steps.  The state after the timed region is
+    therefore warmup + steps steps from the initial fields in every mode, and
+    with fields=True the observables of box 0 are returned for the error
+    against the FP64 run."""
     import torch
 
     from paper_2501_00846_amd import lbm
@@ -131,6 +209,9 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None
         ctx.set_tuning(*tuning)
     elif tune:
         ctx.autotune(steps=max(4, min(20, steps // 10)))
+        # the tuner advanced the state: restart from the initial fields
+        for i, c in enumerate(cases):
+            ctx.init_case(i, c)
     step = ctx.step_unbatched if unbatched else ctx.step
     step(warmup)
     ctx.synchronize()
@@ -156,6 +237,7 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None
     bpl = ctx.bytes_per_update
     diag = ctx.diagnostics(0)
     tuning = ctx.tuning()
+    obs = ctx.fields(0) if fields else None
     ctx.close()
     mlups = nodes * steps / wall / 1e6
     achieved = nodes * bpl / (kern_ms * 1e-3) / 1e9
@@ -163,7 +245,19 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None
                 kernel_ms_segments=[round(v, 5) for v in seg_ms],
                 kernel_ms_median=float(np.median(seg_ms)), nodes=nodes,
                 bytes_per_update=bpl, achieved_gbs=achieved, frac=achieved / PEAK_HBM_GBS,
-                tuning=tuning, phase_mass=diag["phase_mass"], nonfinite=diag["nonfinite"])
+                tuning=tuning, phase_mass=diag["phase_mass"], nonfinite=diag["nonfinite"],
+                fields=obs)
+
+
+def field_errors(got, ref):
+    """Per-field error of a run against the FP64 run of the same step count:
+    relative L2 and max norms of phi, rho, u_x, u_y, u_z and p."""
+    out = {}
+    for name in ("phi", "rho", "p"):
+        out[name] = _rel(got[name], ref[name])
+    for c, cn in enumerate("xyz"):
+        out["u" + cn] = _rel(got["u"][c], ref["u"][c])
+    return {k: {kk: float("%.3g" % vv) for kk, vv in v.items()} for k, v in out.items()}
 
 
 def cpu_baseline(config):
@@ -371,17 +465,45 @@ def summarize_counters(args):
     print(json.dumps(data[key]))
 
 
+def summarize_valu(args):
+    """SQ_INSTS_VALU of the fused step from a rocprofv3 --pmc run into
+    profiles/valu.json, as wave instructions per wave-plane of the launch the
+    counters were taken with (--tuning)."""
+    valu = _read_counter_csv(args.valu_csv, "SQ_INSTS_VALU", "fused_step")
+    if not args.tuning:
+        raise SystemExit("--summarize-valu needs the --tuning the counters were taken with")
+    t = [int(v) for v in args.tuning.split(",")]
+    tuning = {"block_x": t[0], "block_y": t[1], "z_chunk": t[2]}
+    cases, _ = make_cases(args.config)
+    gc = args.closure == "gradient"
+    planes = wave_planes([c.problem for c in cases], tuning)
+    prec = args.precision.split(",")[0]
+    key = valu_key(args.config + ("/gc" if gc else ""), prec, tuning)
+    path = getattr(args, "valu_json", None) or VALU_JSON
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    nodes = sum(c.problem.n_nodes for c in cases)
+    data[key] = {"kernel_hash": kernel_hash(), "tuning": t[:3], "valu_per_dispatch": valu,
+                 "wave_planes": planes, "valu_per_wave_plane": valu / planes,
+                 "valu_per_update": valu * 64 / nodes}
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    print(json.dumps(data[key]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the workload's own run length, 400 for the second workloads)")
     ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C4", "C5", "raindrop", "eoga"])
+    ap.add_argument("--config", default="C5", choices=["C1", "C2", "C3", "C4", "C5", "raindrop", "eoga"])
     ap.add_argument("--precision", default=None,
-                    help="comma list of fp64,fp32,fp16_os,bf16_os (default depends on config)")
+                    help="comma list of fp64,fp32,fp16_os,bf16_os (default depends on config; the first "
+                         "is the headline)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-error", action="store_true",
+                    help="skip the per-field error against the FP64 run")
     ap.add_argument("--unbatched", action="store_true", help="C4: one launch per box per step")
     ap.add_argument("--precision-study", action="store_true",
                     help="per-field errors of the reduced-precision modes against FP64")
@@ -389,10 +511,13 @@ def main():
                     help="only run REPS plain 1 GiB device copies (counter calibration)")
     ap.add_argument("--summarize-counters", action="store_true",
                     help="write profiles/traffic.json from rocprofv3 counter CSVs")
+    ap.add_argument("--summarize-valu", action="store_true",
+                    help="write profiles/valu.json from a rocprofv3 SQ_INSTS_VALU counter CSV")
     ap.add_argument("--fetch-csv")
     ap.add_argument("--write-csv")
     ap.add_argument("--copy-fetch-csv")
     ap.add_argument("--copy-write-csv")
+    ap.add_argument("--valu-csv")
     ap.add_argument("--copy-kernel", default="elementwise")
     ap.add_argument("--closure", default="moment", choices=["moment", "gradient"],
                     help="a2 from the stored second moment (the paper's algorithm) or from the "
@@ -410,6 +535,9 @@ def main():
     if args.summarize_counters:
         summarize_counters(args)
         return
+    if args.summarize_valu:
+        summarize_valu(args)
+        return
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the path is a single-GPU kernel; multi-GPU slab "
@@ -417,48 +545,87 @@ def main():
         sys.exit(2)
 
     defaults = {"C1": "fp64", "C2": "fp64,fp32", "C3": "fp32,fp16_os,bf16_os", "C4": "fp32",
-                "C5": "fp32,fp16_os,fp64", "raindrop": "fp32", "eoga": "fp32"}
+                "C5": "fp64,fp32,fp16_os", "raindrop": "fp32", "eoga": "fp32"}
     if args.steps is None:
         # each workload is timed over its own run length
         args.steps = {"C1": 500, "C2": 20000, "C3": 5000, "C4": 2000, "C5": 2000}.get(args.config, 400)
     precisions = (args.precision or defaults[args.config]).split(",")
     log("bench: building cases for %s" % args.config)
     cases, desc = make_cases(args.config)
-    if args.closure == "gradient":
+    gc = args.closure == "gradient"
+    if gc:
         for c in cases:
             c.problem.gradient_closure = True
         desc += ", gradient closure (state phi, P, J)"
+    cfg_key = args.config + ("/gc" if gc else "")
+    problems = [c.problem for c in cases]
+    # per-field error against the FP64 run: only for single-box workloads
+    # that run FP64 among their modes
+    errors = (not args.no_error and not args.unbatched and "fp64" in precisions and len(cases) == 1
+              and len(precisions) > 1)
+    order = (["fp64"] + [p for p in precisions if p != "fp64"]) if errors else precisions
     modes = {}
-    for prec in precisions:
+    ref_fields = None
+    tuning_arg = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+    for prec in order:
         log("bench: %s %s: %d warmup + %d timed steps" % (args.config, prec, args.warmup, args.steps))
-        tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
-        modes[prec] = run_mode(cases, prec, args.steps, args.warmup, not args.no_tune, args.unbatched, tuning)
+        m = run_mode(cases, prec, args.steps, args.warmup, not args.no_tune, args.unbatched, tuning_arg,
+                     fields=errors)
+        obs = m.pop("fields")
+        if errors:
+            if prec == "fp64":
+                ref_fields = obs
+            else:
+                m["error_vs_fp64"] = field_errors(obs, ref_fields)
+                log("bench: %s error vs fp64 after %d steps: phi %.2e rho %.2e uz %.2e p %.2e (rel L2)" % (
+                    prec, args.warmup + args.steps, m["error_vs_fp64"]["phi"]["l2"],
+                    m["error_vs_fp64"]["rho"]["l2"], m["error_vs_fp64"]["uz"]["l2"],
+                    m["error_vs_fp64"]["p"]["l2"]))
+            del obs
+        m["alu"] = alu_ceiling(valu_per_launch(cfg_key, prec, problems, m["tuning"]), m["nodes"],
+                               m["kernel_ms"])
+        modes[prec] = m
         log("bench: %s %s: %.0f MLUPS, kernel %.3f ms/step, %.0f GB/s (%.1f%% of HBM peak)" % (
-            args.config, prec, modes[prec]["mlups"], modes[prec]["kernel_ms"], modes[prec]["achieved_gbs"],
-            100 * modes[prec]["frac"]))
+            args.config, prec, m["mlups"], m["kernel_ms"], m["achieved_gbs"], 100 * m["frac"]))
+    ref_fields = None
     if args.config == "C4" and not args.unbatched:
         # the unbatched baseline: one launch per box per step (no graphs)
         prec = precisions[0]
         log("bench: C4 %s unbatched baseline" % prec)
-        modes[prec + "_unbatched"] = run_mode(cases, prec, args.steps, args.warmup, False, True,
-                                              tuple(modes[prec]["tuning"].values()))
-        log("bench: C4 unbatched: %.0f MLUPS" % modes[prec + "_unbatched"]["mlups"])
+        mu = run_mode(cases, prec, args.steps, args.warmup, False, True,
+                      tuple(modes[prec]["tuning"].values()))
+        mu.pop("fields")
+        modes[prec + "_unbatched"] = mu
+        log("bench: C4 unbatched: %.0f MLUPS" % mu["mlups"])
     head = precisions[0]
     m = modes[head]
-    traffic = measured_traffic(args.config + ("/gc" if args.closure == "gradient" else ""), head, m["tuning"])
+    traffic = measured_traffic(cfg_key, head, m["tuning"])
     copy_gbs = copy_bandwidth()
     log("bench: device copy %.0f GB/s" % copy_gbs)
-    roof = {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(m["frac"], 4), "traffic": traffic,
-            "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(m["achieved_gbs"] / copy_gbs, 4),
-            "kernel": "fused_step (%s)" % head, "bytes_per_update": m["bytes_per_update"],
-            "nodes_per_launch": m["nodes"]}
+    hbm_floor_ms = m["nodes"] * m["bytes_per_update"] / (PEAK_HBM_GBS * 1e9) * 1e3
+    alu = m["alu"]
+    # the roofline that bounds the kernel: the larger of the HBM floor
+    # (algorithmic bytes at 8 TB/s) and the vector-ALU floor
+    bound = "alu" if (alu is not None and alu["floor_ms"] > hbm_floor_ms) else "hbm"
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(m["frac"], 4)}
+    else:
+        roof = {"bound": "alu", "achieved": alu["achieved_ginst_s"], "peak": alu["issue_peak_ginst_s"],
+                "unit": "G VALU wave-instructions/s", "frac": alu["frac"],
+                "hbm_achieved_gbs": round(m["achieved_gbs"], 1), "hbm_frac": round(m["frac"], 4)}
+    roof.update({"traffic": traffic, "copy_gbs": round(copy_gbs, 1),
+                 "frac_of_copy": round(m["achieved_gbs"] / copy_gbs, 4),
+                 "hbm_floor_ms": round(hbm_floor_ms, 4), "alu": alu,
+                 "kernel": "fused_step (%s)" % head, "kernel_ms": round(m["kernel_ms"], 4),
+                 "bytes_per_update": m["bytes_per_update"], "nodes_per_launch": m["nodes"]})
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(args.config)
     out = {
-        "metric": "MLUPS (million lattice updates per second) of the fused thread-safe LB + Allen-Cahn step",
+        "metric": "MLUPS (million lattice updates per second) of the fused thread-safe LB + Allen-Cahn step, "
+                  "with % of HBM roofline; reduced-precision storage modes with their per-field error vs FP64",
         "value": round(m["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -466,13 +633,12 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(m["ms_per_step"], 4),
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": None,
         "vs_baseline": None,
         "dtype": DTYPE[head],
         "data": "synthetic (seeded initial droplet/bubble fields)",
         "config": {"workload": desc, "config": args.config, "closure": args.closure, "nodes": m["nodes"],
-                   "precision": head,
-                   "tuning": m["tuning"], "steps_per_launch": 1},
+                   "precision": head, "tuning": m["tuning"], "steps_per_launch": 1},
         "roofline": roof,
         "cpu_baseline": cpu,
         "modes": {p: {"mlups": round(v["mlups"], 1), "kernel_ms": round(v["kernel_ms"], 4),
@@ -480,6 +646,7 @@ def main():
                       "kernel_ms_segments": v["kernel_ms_segments"],
                       "achieved_gbs": round(v["achieved_gbs"], 1), "frac": round(v["frac"], 4),
                       "bytes_per_update": v["bytes_per_update"], "tuning": v["tuning"],
+                      "alu": v.get("alu"), "error_vs_fp64": v.get("error_vs_fp64"),
                       "nonfinite": v["nonfinite"]} for p, v in modes.items()},
         "paper_context": PAPER_CONTEXT,
     }

@@ -141,8 +141,14 @@ typedef struct {
 } lbm_tuning;
 
 /* Create a context holding n_boxes >= 1 independent boxes stepped together
- * (one launch per step covers every box).  All parameters are validated before
- * any device call.  The state is undefined until lbm_init_phase or
+ * (one launch per step covers every box).  Each lbm_params is the paper's
+ * statement of one problem: the grid and the D3Q27 lattice (Sec. II.B, Eq.
+ * lbe), the two phases' densities and viscosities (Sec. II.A, Eq. NSeq; the
+ * density law below Eq. press_corr), the surface tension through beta and
+ * kappa of the chemical potential (Sec. II.C), the Allen-Cahn diffusivity D
+ * and interface width delta (Sec. II.A), the body force on the light phase
+ * and the no-slip walls (Sec. III.A, III.D).  All parameters are validated
+ * before any device call.  The state is undefined until lbm_init_phase or
  * lbm_set_state has been called for every box.  On success *out owns all
  * device memory of the state (2 x 11 fields per box, ping-pong; 2 x 5 with
  * LBM_GRADIENT_CLOSURE).  On the device each stored row of nx nodes is padded
@@ -158,7 +164,16 @@ lbm_status lbm_init_phase(lbm_ctx* ctx, int32_t box, const double* phi, const do
                           const double* pstar);
 
 /* Enqueue nsteps >= 0 time steps of every box on the context stream
- * (replayed from a captured hipGraph when graphs are enabled). Asynchronous. */
+ * (replayed from a captured hipGraph when graphs are enabled). Asynchronous.
+ * One step is the four phases of Sec. II.D: moments and forces (Eqs.
+ * moments0, moments1, press_corr, jaqminforce, visc_corr), pre-regularisation
+ * (Eq. hermite_neq2), the fused stream-collide (Eqs. LBexp, pushLB, eqts,
+ * noneqts, guoforce), taken as a pull so that each thread writes only its
+ * own node (the thread-safe principle of Sec. II.B), and the FTCS update of
+ * the conservative Allen-Cahn equation (Sec. II.A, update formula of
+ * Sec. II.D).  Errors: LBM_ERR_STATE if a box has no state yet;
+ * LBM_ERR_DEVICE if a launch fails.  A step that goes non-finite is reported
+ * by the next lbm_get_fields / lbm_diagnostics. */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* Observables of one box (Sec. II.C): rho = rho_l phi + (1-phi) rho_g,
@@ -168,7 +183,13 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
 lbm_status lbm_get_fields(lbm_ctx* ctx, int32_t box, double* rho, double* u, double* phi,
                           double* p);
 
-/* FP64 reductions of one box.  Synchronises; LBM_ERR_UNSTABLE if nonfinite. */
+/* FP64 reductions of one box: phase mass and sum p* (conserved by the flux
+ * form of Sec. II.A and the moments of Eq. moments0), momentum and kinetic
+ * energy with u = J + a/2 (Eq. moments1), the centroid and centre-of-mass
+ * velocity of each phase (the bubble rise velocity compared in Sec. III.A,
+ * Fig. comparison), and the bulk pressures p = rho cs^2 p* (Sec. II.C, below
+ * Eq. press_corr) from which the Laplace jump is read.  *out is written
+ * whenever the reduction ran.  Synchronises; LBM_ERR_UNSTABLE if nonfinite. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, int32_t box, lbm_diag* out);
 
 /* Raw state of one box as 11 N-double planes in the order
@@ -186,8 +207,16 @@ lbm_status lbm_get_state_points(lbm_ctx* ctx, int32_t box, int64_t n, const int6
 
 /* Offset-and-scale encoding of the 10 moments of one box in the 16-bit
  * storage modes: stored = (value - offset[k]) * scale[k], k over P, Jx, Jy, Jz,
- * Qxx, Qyy, Qzz, Qxy, Qxz, Qyz.  scale must be a positive power of two.
- * Takes effect for the next init/set_state; ignored in FP64/FP32 modes. */
+ * Qxx, Qyy, Qzz, Qxy, Qxz, Qyz.  scale must be a positive power of two and
+ * offset finite.  Without a call, offsets are 0 and scales 1024 (P), 4096
+ * (J), 65536 (Q).  If the box already holds a state, that state is re-encoded
+ * on the device (decoded with the previous offsets and scales, encoded with
+ * the new ones), so its values change only by the rounding of the new
+ * encoding; the next step uses the new encoding.  If the re-encoding fails on
+ * the device (LBM_ERR_DEVICE), the box has no valid state until the next
+ * lbm_init_phase / lbm_set_state.  Synchronises.  Ignored in
+ * the FP64 and FP32 modes (returns LBM_OK).  The storage precision is the
+ * paper's silence: Sec. II.B fixes the moment set, not its format. */
 lbm_status lbm_set_encoding(lbm_ctx* ctx, int32_t box, const double* offset,
                             const double* scale);
 

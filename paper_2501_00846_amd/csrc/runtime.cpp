@@ -578,9 +578,35 @@ lbm_status lbm_set_encoding(lbm_ctx* c, int32_t box, const double* offset, const
     if (!std::isfinite(offset[k])) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: offset[%d] must be finite", k);
   }
   Box& b = c->boxes[box];
+  if (c->precision != LBM_FP16_OS && c->precision != LBM_BF16_OS) return LBM_OK;
+  const BoxDesc before = b.desc;
+  double keep_off[10], keep_scale[10];
   for (int k = 0; k < 10; ++k) {
+    keep_off[k] = b.enc_off[k];
+    keep_scale[k] = b.enc_scale[k];
     b.enc_off[k] = offset[k];
     b.enc_scale[k] = scale[k];
+  }
+  fill_desc(b, c->precision);
+  if (b.initialized) {
+    // re-encode the live moments: decode each field with the previous
+    // encoding into the staging buffer, encode it again with the new one
+    lbm_status st = ensure_stage(c, b.n);
+    for (int k = 0; st == LBM_OK && k < b.desc.nmom; ++k) {
+      hipError_t e = lbm::launch_decode(c->precision, before, c->parity, 1 + k, c->d_stage, b.n, c->stream);
+      if (e == hipSuccess) e = lbm::launch_encode(c->precision, b.desc, c->parity, 1 + k, c->d_stage, b.n, c->stream);
+      if (e != hipSuccess) st = fail(c, LBM_ERR_DEVICE, "lbm_set_encoding: re-encoding failed: %s", hipGetErrorString(e));
+    }
+    if (st != LBM_OK) {
+      // the state may be partly re-encoded: it no longer matches either encoding
+      for (int k = 0; k < 10; ++k) {
+        b.enc_off[k] = keep_off[k];
+        b.enc_scale[k] = keep_scale[k];
+      }
+      b.initialized = false;
+      (void)upload_boxes(c);
+      return st;
+    }
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return upload_boxes(c);

@@ -70,24 +70,34 @@ def _bf16_round(x32):
     return (b.astype(np.uint32) << 16).view(np.float32)
 
 
-def quantize(values, precision, field):
-    """Stored-and-decoded value of `values` for field index (0 = phi, 1..10 moments)."""
+def quantize(values, precision, field, offset=None, scale=None):
+    """Stored-and-decoded value of `values` for field index (0 = phi, 1..10 moments).
+
+    The 16-bit modes store (f32(v) - offset) * scale rounded to FP16 / BF16
+    (the subtraction rounded to FP32, the power-of-two scale exact) and decode
+    f32(stored) * (1/scale) + offset in FP32 (the product is exact, so a fused
+    multiply-add and a separate add round alike).  offset / scale: the 10
+    per-moment values of lbm_set_encoding (default 0 and DEFAULT_SCALE)."""
     v = np.asarray(values, dtype=np.float64)
     if precision == "fp64":
         return v.copy()
     f32 = v.astype(np.float32)
     if precision == "fp32" or field == 0:
         return f32.astype(np.float64)
-    s = np.float32(DEFAULT_SCALE[field - 1])
+    off = np.float32(0.0 if offset is None else offset[field - 1])
+    s = np.float32(DEFAULT_SCALE[field - 1] if scale is None else scale[field - 1])
+    x = (f32 - off) * s
     if precision == "fp16_os":
-        return (f32 * s).astype(np.float16).astype(np.float32).astype(np.float64) / float(s)
-    if precision == "bf16_os":
-        return _bf16_round(f32 * s).astype(np.float64) / float(s)
-    raise ValueError(precision)
+        h = x.astype(np.float16).astype(np.float32)
+    elif precision == "bf16_os":
+        h = _bf16_round(x)
+    else:
+        raise ValueError(precision)
+    return (h * (np.float32(1.0) / s) + off).astype(np.float64)
 
 
-def quantize_state(state, precision):
-    return np.stack([quantize(state[k], precision, k) for k in range(11)])
+def quantize_state(state, precision, offset=None, scale=None):
+    return np.stack([quantize(state[k], precision, k, offset, scale) for k in range(11)])
 
 
 # relative half-ulp of the storage format per field
@@ -150,7 +160,7 @@ def sample_points(prob, rng, n_random=24, extra=()):
     return sorted({(clamp(x, nx), clamp(y, ny), clamp(z, nz)) for x, y, z in pts})
 
 
-def field_tolerance(precision, ref):
+def field_tolerance(precision, ref, offset=None):
     """Per-field absolute tolerance for one step from the same stored state.
 
     FP64: 1e-12 of the field scale.  Reduced precision (FP32 arithmetic, FP64
@@ -159,7 +169,9 @@ def field_tolerance(precision, ref):
     signed sum of populations of that size, and the chemical potential is a
     near-cancelling difference whose FP32 rounding is amplified by 1/rho_g in
     the light phase (measured up to 3e-6 of that scale for density ratio
-    1000) -- plus one storage half-ulp of the value.  ref may be (11, ...)."""
+    1000) -- plus one storage half-ulp of the stored value (v - offset) in the
+    16-bit modes (offset: the 10 per-moment offsets, default 0).  ref may be
+    (11, ...)."""
     ref = np.asarray(ref)
     tol = np.empty_like(ref)
     s_mom = max(np.abs(ref[1]).max(), np.abs(ref[2:5]).max())
@@ -170,5 +182,6 @@ def field_tolerance(precision, ref):
         elif k == 0:
             tol[k] = 2e-5 * scale + 1.01 * storage_rel(precision, k) * np.abs(ref[k]) + 1e-300
         else:
-            tol[k] = 1e-5 * max(scale, s_mom) + 1.01 * storage_rel(precision, k) * np.abs(ref[k]) + 1e-300
+            off = 0.0 if offset is None or precision not in ("fp16_os", "bf16_os") else offset[k - 1]
+            tol[k] = 1e-5 * max(scale, s_mom) + 1.01 * storage_rel(precision, k) * np.abs(ref[k] - off) + 1e-300
     return tol

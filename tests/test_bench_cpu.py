@@ -7,6 +7,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 import bench
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -88,3 +90,55 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_wave_planes_counts_items_planes_and_waves():
+    """34 x 15 workgroups (8 wavefronts) with 32 x 13 output columns: a
+    64 x 26 x 10 box has 4 tile columns; z-chunks of 4 give items over output
+    planes [0,4), [4,8), [8,10), each marching one staging plane on either
+    side (6 + 6 + 4 planes) unless that side is a z wall (5 + 6 + 3)."""
+    from paper_2501_00846_amd.workloads import Problem, WALL
+
+    t = {"block_x": 34, "block_y": 15, "z_chunk": 4}
+    assert bench.wave_planes([Problem(64, 26, 10)], t) == 4 * 16 * 8
+    assert bench.wave_planes([Problem(64, 26, 10, bc=(0, 0, WALL))], t) == 4 * 14 * 8
+    # ragged x and y: 65 columns need 3 tiles, 27 rows 3; a chunk longer than nz is nz
+    t2 = {"block_x": 32, "block_y": 8, "z_chunk": 64}
+    assert bench.wave_planes([Problem(65, 19, 5)], t2) == 3 * 4 * (5 + 2) * 4
+    # boxes of an ensemble add up
+    assert bench.wave_planes([Problem(64, 26, 10), Problem(64, 26, 10)], t) == 2 * 4 * 16 * 8
+
+
+def test_alu_ceiling_and_valu_lookup(tmp_path):
+    """The ALU floor is the VALU wave-instruction count over 256 CUs x 4 SIMDs
+    x 2.4 GHz / 4; the committed count is scaled by wave-planes and reported
+    only for the same kernel source and tile shape."""
+    assert bench.VALU_ISSUE_PER_S == 614.4e9
+    a = bench.alu_ceiling(614.4e9 * 1e-3, 1 << 20, 2.0)  # 1 ms of issue in a 2 ms kernel
+    assert a["floor_ms"] == 1.0 and a["frac"] == 0.5
+    assert a["ceiling_mlups"] == round((1 << 20) / 1e-3 / 1e6, 1)
+    assert bench.alu_ceiling(None, 1, 1.0) is None
+    from paper_2501_00846_amd.workloads import Problem
+
+    probs = [Problem(64, 26, 10)]
+    t = {"block_x": 34, "block_y": 15, "z_chunk": 4}
+    path = tmp_path / "valu.json"
+    json.dump({bench.valu_key("C9", "fp32", t): {"kernel_hash": bench.kernel_hash(),
+                                                 "valu_per_wave_plane": 600.0}}, open(path, "w"))
+    assert bench.valu_per_launch("C9", "fp32", probs, t, path=str(path)) == 600.0 * 4 * 16 * 8
+    # another z-chunk of the same shape scales by its own wave-planes
+    t8 = dict(t, z_chunk=8)
+    assert bench.valu_per_launch("C9", "fp32", probs, t8, path=str(path)) == 600.0 * bench.wave_planes(probs, t8)
+    assert bench.valu_per_launch("C9", "fp64", probs, t, path=str(path)) is None
+    assert bench.valu_per_launch("C9", "fp32", probs, dict(t, block_x=32, block_y=8), path=str(path)) is None
+
+
+def test_field_errors_are_relative_norms():
+    rng = np.random.default_rng(0)
+    ref = {"phi": rng.uniform(0, 1, (4, 5, 6)), "rho": rng.uniform(0.1, 1, (4, 5, 6)),
+           "p": rng.normal(size=(4, 5, 6)), "u": rng.normal(size=(3, 4, 5, 6))}
+    got = {k: v.copy() for k, v in ref.items()}
+    got["u"][2] *= 1.001
+    e = bench.field_errors(got, ref)
+    assert e["phi"]["l2"] == 0 and e["ux"]["max"] == 0
+    assert abs(e["uz"]["l2"] - 1e-3) < 1e-9 and abs(e["uz"]["max"] - 1e-3) < 1e-9

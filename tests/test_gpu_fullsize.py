@@ -64,14 +64,14 @@ def test_rising_bubble_128x128x256_one_step(precision):
     _check(case, precision, extra=extra)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16_os"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16_os"])
 def test_drop_into_pool_512_one_step(precision):
     case = workloads.drop_into_pool()
     extra = [(256, 256, 127), (256, 256, 128), (256, 256, 220), (256, 256, 300), (0, 0, 511), (511, 511, 0)]
     _check(case, precision, tune=True, extra=extra)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16_os"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16_os", "bf16_os"])
 def test_droplet_collision_256_one_step(precision):
     case = workloads.droplet_collision()
     extra = [(120, 128, 128), (136, 128, 128), (128, 128, 128), (96, 128, 128), (160, 128, 128)]
@@ -81,11 +81,9 @@ def test_droplet_collision_256_one_step(precision):
 def test_ensemble_64_boxes_one_launch_one_step():
     """All 64 boxes of uneven sizes in one launch per step, in the tile shape
     and z-chunk the FP32 benchmark autotunes to, each box checked at sampled
-    nodes against the per-node oracle.  The check runs in FP64 (1e-12 of each
-    box's population scale): the droplets start at rest, so one step moves P
-    and J by amounts far below FP32 rounding of the forces; the FP32 batched
-    launch is checked bitwise against separate single-box launches
-    elsewhere."""
+    nodes against the per-node oracle, in FP64 (1e-12 of each box's
+    population scale).  The FP32 form of the same launch is checked by
+    test_ensemble_64_boxes_fp32_from_developed_state below."""
     cases = workloads.ensemble()
     with lbm.Context([c.problem for c in cases], "fp32") as ctx:
         for i, c in enumerate(cases):
@@ -110,3 +108,107 @@ def test_ensemble_64_boxes_one_launch_one_step():
                 err = np.abs(got[k] - refa[k]).max()
                 assert err <= 1e-12 * scale, (i, name, err, scale)
         _log("64 boxes checked")
+
+
+def _state_reference(prob, state, pts):
+    """Per-node oracle step at pts from a full (11, nz, ny, nx) state."""
+    st = LazyState(state[0], state[1], tuple(state[2:5]), tuple(state[5:11]))
+    ref = PW.step_points(st, prob, pts)
+    return np.concatenate([ref["phi"][None], ref["P"][None], ref["J"].T,
+                           np.stack([ref["Q"][:, 0, 0], ref["Q"][:, 1, 1], ref["Q"][:, 2, 2],
+                                     ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
+
+
+def test_ensemble_64_boxes_fp32_from_developed_state():
+    """The 64-box ensemble in FP32, one launch per step in the tile shape and
+    z-chunk the FP32 benchmark autotunes to.  The boxes first run 60 FP64
+    steps from their seeded fields, so the drops oscillate and carry flow
+    (from rest, one step moves P and J by less than FP32 rounding of the
+    forces); that state, stored in FP32, is stepped once and every box is
+    checked at sampled nodes against the per-node oracle on the same stored
+    values, to the FP32 tolerance."""
+    from tests.gpu_util import quantize_state
+
+    cases = workloads.ensemble()
+    probs = [c.problem for c in cases]
+    with lbm.Context(probs, "fp64") as ctx:
+        for i, c in enumerate(cases):
+            ctx.init_case(i, c)
+        ctx.step(60)
+        states = [quantize_state(ctx.get_state(i), "fp32") for i in range(len(cases))]
+    _log("ensemble: 60 FP64 steps done")
+    with lbm.Context(probs, "fp32") as ctx:
+        for i, st in enumerate(states):
+            ctx.set_state(i, st.reshape(-1))
+        ctx.autotune(2)
+        _log("ensemble fp32 tuning %s" % ctx.tuning())
+        for i, st in enumerate(states):
+            ctx.set_state(i, st.reshape(-1))
+        ctx.step(1)
+        rng = np.random.default_rng(78)
+        for i, c in enumerate(cases):
+            pts = sample_points(c.problem, rng, n_random=4)
+            got = ctx.state_at(i, pts)
+            refa = _state_reference(c.problem, states[i], pts)
+            tols = field_tolerance("fp32", refa)
+            for k, name in enumerate(FIELDS):
+                err = np.abs(got[k] - refa[k])
+                assert (err <= tols[k]).all(), (i, name, float(err.max()), float(tols[k].max()))
+    _log("64 boxes checked in FP32")
+
+
+class _F64:
+    """Read-only view of an FP32 array whose elements read as FP64 scalars, so
+    that the per-node oracle computes in FP64 on FP32-stored inputs."""
+
+    def __init__(self, a):
+        self.a = a
+        self.shape = a.shape
+
+    def __getitem__(self, key):
+        return np.float64(self.a[key])
+
+
+def test_raindrop_train_fp32_one_step():
+    """The raindrop train of Sec. III.D at the benchmark's size (500 x 500 x
+    3000, walls on +-z), FP32, in the launch configuration of the benchmark's
+    sweep (34 x 15 workgroups, z-chunk 128).  Its inputs are built in FP32, so
+    they are stored exactly.  One step, sampled nodes (substrate, drops,
+    interfaces, top wall) against the per-node oracle."""
+    case = workloads.raindrop_train(dtype=np.float32)
+    prob = case.problem
+    pts = sample_points(prob, np.random.default_rng(31), n_random=12,
+                        extra=[(250, 250, 0), (250, 250, 1), (250, 250, 75), (250, 250, 50),
+                               (250, 250, 100), (225, 250, 75), (250, 250, 2999), (499, 499, 2998)])
+    _log("raindrop train %dx%dx%d fp32: %d sampled nodes" % (prob.nx, prob.ny, prob.nz, len(pts)))
+    with lbm.Context(prob, "fp32") as ctx:
+        ctx.set_tuning(34, 15, 128, 0)
+        ctx.init_case(0, case)
+        ctx.step(1)
+        got = ctx.state_at(0, pts)
+    st = LazyState(_F64(case.phi), None, tuple(_F64(case.u[a]) for a in range(3)))
+    ref = PW.step_points(st, prob, pts)
+    refa = np.concatenate([ref["phi"][None], ref["P"][None], ref["J"].T,
+                           np.stack([ref["Q"][:, 0, 0], ref["Q"][:, 1, 1], ref["Q"][:, 2, 2],
+                                     ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
+    _compare(got, refa, "fp32")
+
+
+def test_eo_ga_sweep_fp32_one_step():
+    """The twelve Eo-Ga bubbles (Sec. III.A) at the benchmark's size (200 x
+    200 x 400 each), FP32, in one launch per step in the launch configuration
+    of the benchmark's sweep (32 x 8 workgroups, z-chunk 8).  One step, each
+    box at sampled nodes against the per-node oracle on the FP32-stored
+    inputs."""
+    cases = workloads.eo_ga_sweep()
+    with lbm.Context([c.problem for c in cases], "fp32") as ctx:
+        ctx.set_tuning(32, 8, 8, 0)
+        for i, c in enumerate(cases):
+            ctx.init_case(i, c)
+        ctx.step(1)
+        rng = np.random.default_rng(32)
+        for i, c in enumerate(cases):
+            pts = sample_points(c.problem, rng, n_random=6, extra=[(100, 100, 50), (100, 100, 150)])
+            got = ctx.state_at(i, pts)
+            _log("Eo-Ga box %d (%s)" % (i, c.name))
+            _compare(got, _reference(c, "fp32", pts), "fp32")

@@ -107,19 +107,21 @@ ENSEMBLE = [((24, 30, 27), (P_, P_, P_)), ((40, 9, 33), (W_, P_, P_)), ((7, 5, 9
             ((65, 33, 12), (W_, W_, W_)), ((3, 2, 4), (P_, P_, P_))]
 
 
-def test_ensemble_one_launch_equals_separate_boxes():
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16_os"])
+def test_ensemble_one_launch_equals_separate_boxes(precision):
     """One launch over the tile list of every box equals each box stepped on
-    its own, and equals one launch per box (the unbatched baseline)."""
+    its own, and equals one launch per box (the unbatched baseline), bit for
+    bit in every storage mode."""
     probs = [_prob(d, bc, sigma=0.005 * (i + 1)) for i, (d, bc) in enumerate(ENSEMBLE)]
     states = [smooth_random_state(p, 10 + i) for i, p in enumerate(probs)]
     single = []
     for p, s in zip(probs, states):
-        with lbm.Context(p, "fp64") as ctx:
+        with lbm.Context(p, precision) as ctx:
             ctx.set_state(0, s.reshape(-1))
             ctx.step(4)
             single.append(ctx.get_state(0))
     for mode in ("batched", "unbatched"):
-        with lbm.Context(probs, "fp64") as ctx:
+        with lbm.Context(probs, precision) as ctx:
             for i, s in enumerate(states):
                 ctx.set_state(i, s.reshape(-1))
             if mode == "batched":
@@ -128,6 +130,8 @@ def test_ensemble_one_launch_equals_separate_boxes():
                 ctx.step_unbatched(4)
             for i in range(len(probs)):
                 assert np.array_equal(ctx.get_state(i), single[i]), (mode, i)
+    if precision != "fp64":
+        return
     # and the small boxes against the oracle
     for i in (2, 4):
         ref = oracle_run_state(probs[i], states[i], 4)
