@@ -160,7 +160,7 @@ def sample_points(prob, rng, n_random=24, extra=()):
     return sorted({(clamp(x, nx), clamp(y, ny), clamp(z, nz)) for x, y, z in pts})
 
 
-def field_tolerance(precision, ref, offset=None):
+def field_tolerance(precision, ref, offset=None, force=None):
     """Per-field absolute tolerance for one step from the same stored state.
 
     FP64: 1e-12 of the field scale.  Reduced precision (FP32 arithmetic, FP64
@@ -171,10 +171,20 @@ def field_tolerance(precision, ref, offset=None):
     the light phase (measured up to 3e-6 of that scale for density ratio
     1000) -- plus one storage half-ulp of the stored value (v - offset) in the
     16-bit modes (offset: the 10 per-moment offsets, default 0).  ref may be
-    (11, ...)."""
+    (11, ...).
+
+    force (optional, one value per node of ref, from force_scale): the
+    magnitude of the terms that FP32 arithmetic sums into the acceleration
+    a = F/rho around each node.  Each moment then also gets 4 FP32 rounding
+    units (2^-24) of it: the Laplacian (two roundings of its filtered sums),
+    the chemical-potential difference and its product with grad(phi)/rho each
+    round once, and the populations carry a with weights of order one.  Where
+    the populations themselves are small (a bubble at rest, strong surface
+    tension) this term, not the population scale, bounds the rounding."""
     ref = np.asarray(ref)
     tol = np.empty_like(ref)
     s_mom = max(np.abs(ref[1]).max(), np.abs(ref[2:5]).max())
+    f_term = 0.0 if force is None else 4.0 * 2.0 ** -24 * np.asarray(force)
     for k in range(11):
         scale = np.abs(ref[k]).max()
         if precision == "fp64":
@@ -183,5 +193,61 @@ def field_tolerance(precision, ref, offset=None):
             tol[k] = 2e-5 * scale + 1.01 * storage_rel(precision, k) * np.abs(ref[k]) + 1e-300
         else:
             off = 0.0 if offset is None or precision not in ("fp16_os", "bf16_os") else offset[k - 1]
-            tol[k] = 1e-5 * max(scale, s_mom) + 1.01 * storage_rel(precision, k) * np.abs(ref[k] - off) + 1e-300
+            tol[k] = (1e-5 * max(scale, s_mom) + f_term
+                      + 1.01 * storage_rel(precision, k) * np.abs(ref[k] - off) + 1e-300)
     return tol
+
+
+def _axis_index(i, n, wall):
+    """Node index along an axis of n nodes: periodic wrap, or the half-way
+    mirror of a wall (-1 -> 0, -2 -> 1)."""
+    if not wall:
+        return i % n
+    if i < 0:
+        i = -1 - i
+    elif i >= n:
+        i = 2 * n - 1 - i
+    return min(max(i, 0), n - 1)
+
+
+def force_scale(prob, phi, pstar, pts):
+    """Per sampled node (x, y, z): the largest, over the node and its 26
+    neighbours (whose post-collision populations stream into it), of
+    (|beta4 phi (phi-1)(phi-1/2)| + kappa (6 phi + |lap phi|) + |p*| drho/3)
+    |grad phi| / rho(phi) -- the sizes of the surface-tension and pressure
+    force terms per unit mass before they cancel, with the Laplacian's own
+    summands (6 phi) in place of its value.  phi, pstar: (nz, ny, nx) arrays
+    (or indexable alike; pstar None means 0).  Wall axes mirror."""
+    beta4 = 48.0 * prob.sigma / prob.width
+    kappa = 1.5 * prob.sigma * prob.width
+    drho = prob.rho_l - prob.rho_g
+    dims = (prob.nx, prob.ny, prob.nz)
+    walls = tuple(b == 1 for b in prob.bc)
+    w1 = (1.0, 4.0, 1.0)
+    out = np.empty(len(pts))
+    for j, (x, y, z) in enumerate(pts):
+        idx = [[_axis_index(c + d, dims[a], walls[a]) for d in range(-2, 3)] for a, c in enumerate((x, y, z))]
+        patch = np.array([[[float(phi[zz, yy, xx]) for xx in idx[0]] for yy in idx[1]] for zz in idx[2]])
+        ps = None if pstar is None else np.array(
+            [[[float(pstar[zz, yy, xx]) for xx in idx[0][1:4]] for yy in idx[1][1:4]] for zz in idx[2][1:4]])
+        best = 0.0
+        for kz in range(1, 4):
+            for ky in range(1, 4):
+                for kx in range(1, 4):
+                    c = patch[kz, ky, kx]
+                    g = np.zeros(3)
+                    lap = 0.0
+                    for cz in (-1, 0, 1):
+                        for cy in (-1, 0, 1):
+                            for cx in (-1, 0, 1):
+                                w = w1[cx + 1] * w1[cy + 1] * w1[cz + 1] / 216.0
+                                v = patch[kz + cz, ky + cy, kx + cx]
+                                g += 3.0 * w * v * np.array([cx, cy, cz])
+                                lap += 6.0 * w * (v - c)
+                    rho = prob.rho_g + min(max(c, 0.0), 1.0) * drho
+                    p = 0.0 if ps is None else abs(ps[kz - 1, ky - 1, kx - 1])
+                    t = (abs(beta4 * c * (c - 1.0) * (c - 0.5)) + kappa * (6.0 * abs(c) + abs(lap))
+                         + p * drho / 3.0) * np.linalg.norm(g) / rho
+                    best = max(best, t)
+        out[j] = best
+    return out
