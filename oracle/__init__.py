@@ -19,6 +19,11 @@ It shares no code with the HIP path.  Its only shared input is the seeded
 generator module paper_2501_00846_amd.workloads (initial fields, no method
 arithmetic).
 
+Variants: the gradient closure of a2 (Eq. noneqts, readings G1-G4) and the
+fourth-order phase-field stencils of the higher-order Allen-Cahn update
+(future work at the end of Sec. II.A, readings H1-H3), both in scheme.py and
+pointwise.py.
+
 Readings of places where the paper is silent or garbled are listed in the
 docstring of scheme.py; each function cites the section / equation it follows.
 Parity status: every function here is pinned by tests under tests/ against

@@ -113,6 +113,61 @@ class PointOracle:
         n = q["n"] * np.array([-1.0 if m else 1.0 for m in crossed])
         return q["phi"], u, n
 
+    # -- fourth-order phase-field stencils (scheme.py H1, H3) ------------------
+    def grad4_at(self, x, y, z):
+        """(4 D_1 - D_2)/3 of phi at in-domain node (x, y, z): D_1 over the
+        neighbours x + c_i, D_2 over x + 2 c_i with half the weight."""
+        key = ("g4", x, y, z)
+        if key in self._cache:
+            return self._cache[key]
+        g1 = np.zeros(3)
+        g2 = np.zeros(3)
+        for i in range(NQ):
+            cx, cy, cz = (int(v) for v in C[i])
+            g1 += (W[i] / CS2) * self.phi_at(x + cx, y + cy, z + cz) * C[i]
+            g2 += (W[i] / (2.0 * CS2)) * self.phi_at(x + 2 * cx, y + 2 * cy, z + 2 * cz) * C[i]
+        g = (4.0 * g1 - g2) / 3.0
+        self._cache[key] = g
+        return g
+
+    def flux_parts4(self, x, y, z):
+        """(phi, u, n4) at a node that may be a ghost: the mirrored node's
+        values, u negated per crossed wall, n4's crossed components negated."""
+        xs, mx = self._map(0, x)
+        ys, my = self._map(1, y)
+        zs, mz = self._map(2, z)
+        q = self.node(xs, ys, zs)
+        g = self.grad4_at(xs, ys, zs)
+        n = g / (np.sqrt(np.sum(g ** 2)) + scheme.EPS_NORMAL)
+        crossed = (mx, my, mz)
+        u = q["u"] * (-1.0) ** sum(crossed)
+        n = n * np.array([-1.0 if m else 1.0 for m in crossed])
+        return q["phi"], u, n
+
+    def phase_high_order_at(self, x, y, z):
+        """phi' at (x, y, z) with the fourth-order stencils (scheme.py H1)."""
+        prob = self.prob
+        own = self.node(x, y, z)
+        kac = 4.0 * prob.mobility / prob.width
+        adv = [0.0, 0.0]
+        sharp = [0.0, 0.0]
+        lap = [0.0, 0.0]
+        for i in range(NQ):
+            cx, cy, cz = (int(v) for v in C[i])
+            for s in (1, 2):
+                ph, u, n = self.flux_parts4(x + s * cx, y + s * cy, z + s * cz)
+                wt = W[i] / (s * CS2)
+                adv[s - 1] += wt * ph * float(np.dot(u, C[i]))
+                sharp[s - 1] += wt * ph * (1.0 - ph) * float(np.dot(n, C[i]))
+                lap[s - 1] += (2.0 * W[i] / (s * s * CS2)) * (
+                    self.phi_at(x + s * cx, y + s * cy, z + s * cz) - own["phi"])
+        four = lambda v: (4.0 * v[0] - v[1]) / 3.0
+        if prob.literal_advection:
+            a = float(np.dot(own["u"], self.grad4_at(x, y, z)))
+        else:
+            a = four(adv)
+        return own["phi"] - a + prob.mobility * four(lap) - kac * four(sharp)
+
     # -- one step at one node -------------------------------------------------
     def step_at(self, x, y, z):
         """Returns (phi', P', J'(3), Q'(3x3)) at in-domain node (x, y, z)."""
@@ -149,6 +204,8 @@ class PointOracle:
         else:
             adv = div_adv
         phi_new = own["phi"] - adv + prob.mobility * own["lap"] - kac * div_sharp
+        if getattr(prob, "high_order_ac", False):
+            phi_new = self.phase_high_order_at(x, y, z)
         return phi_new, P, J, Qn
 
 

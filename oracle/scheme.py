@@ -83,6 +83,25 @@ Eq. noneqts, stated there as a velocity-gradient expression):
       moment-based tensor.
   G4  The state is phi, P, J (5 fields); Q is neither stored nor used and is
       kept zero in State.
+
+Higher-order Allen-Cahn variant (Problem.high_order_ac; the higher-order
+discrete derivatives named as future work at the end of Sec. II.A, for which
+the paper gives no scheme):
+  H1  The three discrete derivatives of the phase-field update -- the
+      divergence of the advective and sharpening fluxes, the Laplacian, and
+      the gradient inside the normal n -- are fourth-order: each is the
+      Richardson combination (4 D_1 - D_2)/3 of the isotropic D3Q27 stencil of
+      R6 at spacing 1 (D_1) and the same stencil at spacing 2 (D_2: points
+      x + 2 c_i, same weights, divided by 2 for a first derivative and by 4
+      for the Laplacian).  The leading errors of D_1 and D_2 are isotropic and
+      in the ratio 1 : 4, so the combination cancels them: the gradient is
+      exact on polynomials of degree <= 4 and the Laplacian on degree <= 5.
+  H2  The flow solver is unchanged: the forces (surface tension, pressure and
+      viscous corrections) keep the second-order stencils of Sec. II.C.
+  H3  Ghosts at walls extend R11 to the depth the wider stencils reach:
+      phi(-k) = phi(k - 1) for k = 1..4 (wall axes need at least 4 nodes),
+      ghost velocity minus the mirrored one, ghost normal from the mirrored
+      phi.  The flux divergence still telescopes, so sum phi is conserved.
 """
 from __future__ import annotations
 
@@ -200,6 +219,50 @@ def divergence(vp, h, e=0):
         term = (W[i] / CS2) * sum(float(C[i][a]) * v[a] for a in range(3))
         out = term if out is None else out + term
     return out
+
+
+def grad_wide(fp, h, e=0):
+    """The gradient stencil of R6 at spacing 2: (1/(2 cs^2)) sum_i w_i g(x + 2 c_i) c_i (H1)."""
+    out = None
+    for i in range(NQ):
+        v = shifted(fp, h, 2 * C[i], e)
+        term = (W[i] / (2.0 * CS2)) * C[i].astype(np.float64).reshape(3, 1, 1, 1) * v
+        out = term if out is None else out + term
+    return out
+
+
+def laplacian_wide(fp, h, e=0):
+    """The Laplacian of R6 at spacing 2: (2/(4 cs^2)) sum_i w_i (g(x + 2 c_i) - g(x)) (H1)."""
+    centre = shifted(fp, h, (0, 0, 0), e)
+    out = np.zeros_like(centre)
+    for i in range(NQ):
+        out += (2.0 * W[i] / (4.0 * CS2)) * (shifted(fp, h, 2 * C[i], e) - centre)
+    return out
+
+
+def divergence_wide(vp, h, e=0):
+    """The divergence of R6 at spacing 2: (1/(2 cs^2)) sum_i w_i v(x + 2 c_i) . c_i (H1)."""
+    out = None
+    for i in range(NQ):
+        v = shifted(vp, h, 2 * C[i], e)
+        term = (W[i] / (2.0 * CS2)) * sum(float(C[i][a]) * v[a] for a in range(3))
+        out = term if out is None else out + term
+    return out
+
+
+def grad4(fp, h, e=0):
+    """Fourth-order isotropic gradient (4 D_1 - D_2) / 3 (H1)."""
+    return (4.0 * grad(fp, h, e) - grad_wide(fp, h, e)) / 3.0
+
+
+def laplacian4(fp, h, e=0):
+    """Fourth-order isotropic Laplacian (4 L_1 - L_2) / 3 (H1)."""
+    return (4.0 * laplacian(fp, h, e) - laplacian_wide(fp, h, e)) / 3.0
+
+
+def divergence4(vp, h, e=0):
+    """Fourth-order isotropic divergence (4 D_1 - D_2) / 3 (H1)."""
+    return (4.0 * divergence(vp, h, e) - divergence_wide(vp, h, e)) / 3.0
 
 
 # ----------------------------------------------------------------------------
@@ -427,6 +490,29 @@ def phase_update(st, nf, u, prob):
     return st.phi - adv + M * nf["lap_phi"] - kac * divergence(sharp, 1)
 
 
+def phase_update_high_order(st, u, prob):
+    """The FTCS step of phase_update with the fourth-order derivatives of H1
+    (ghosts H3):
+
+    phi' = phi - div4(phi u) + M lap4(phi) - kappa_AC div4(phi (1 - phi) n4),
+    n4 = grad4(phi) / (|grad4(phi)| + eps).
+    The fluxes are needed up to two nodes beyond the box (the reach of
+    div4), their normals up to four (the reach of grad4 from there).
+    """
+    M = prob.mobility
+    kac = 4.0 * M / prob.width
+    phip = pad(st.phi, prob, 4)
+    phi2 = shifted(phip, 4, (0, 0, 0), 2)               # phi on interior + 2 ghost layers
+    n2 = normal(grad4(phip, 4, 2))                       # ghost normals from mirrored phi
+    up = np.stack([pad(u[a], prob, 2, odd=(True, True, True)) for a in range(3)])
+    sharp = phi2 * (1.0 - phi2) * n2
+    if prob.literal_advection:
+        adv = np.sum(u * grad4(phip, 4), axis=0)
+    else:
+        adv = divergence4(phi2 * up, 2)
+    return st.phi - adv + M * laplacian4(phip, 4) - kac * divergence4(sharp, 2)
+
+
 def step(st, prob):
     """One full time step, phases 1-4 of Sec. II.D."""
     nf = node_fields(st, prob)
@@ -438,7 +524,10 @@ def step(st, prob):
     P, J, Q = moments(f)
     if prob.gradient_closure:
         Q = np.zeros_like(Q)  # G4
-    phi = phase_update(st, nf, u, prob)
+    if getattr(prob, "high_order_ac", False):
+        phi = phase_update_high_order(st, u, prob)
+    else:
+        phi = phase_update(st, nf, u, prob)
     return State(phi, P, J, Q)
 
 

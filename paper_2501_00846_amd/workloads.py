@@ -44,6 +44,7 @@ class Problem:
     rho_ref: float = 0.0      # body force density is (rho - rho_ref) * gravity
     literal_advection: bool = False  # u.grad(phi) instead of div(phi u)
     gradient_closure: bool = False   # a2 from the velocity gradient; state phi, P, J only
+    high_order_ac: bool = False      # fourth-order stencils in the phase-field update
 
     @property
     def shape(self):
