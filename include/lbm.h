@@ -249,6 +249,44 @@ double lbm_bytes_per_update(const lbm_ctx* ctx);
 /* Total nodes over all boxes. */
 int64_t lbm_total_nodes(const lbm_ctx* ctx);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): enqueue
+ * nsteps >= 0 fused steps of ONE box whose state lives in device buffers the
+ * caller owns, with no context and no allocation of any kind.  The step is
+ * the one lbm_step runs (same kernels, bitwise the same results); only the
+ * descriptor and the tile list it reads live in a fixed array of the library
+ * (1 MiB of device memory per GPU, held until the process ends; at most
+ * 32,736 tiles, else LBM_ERR_ARG: use a larger z_chunk).
+ *
+ * box: parameters, checked as by lbm_create (the precision is the storage).
+ * tuning: launch configuration as in lbm_set_tuning, or NULL (34 x 15 tiles,
+ *   a z-chunk that fills the GPU and fits the tile limit).
+ * phi[s], mom[s], s = 0, 1: the two ping-pong state buffers, each aligned to
+ *   its element size (64-byte alignment enables the non-temporal stores):
+ *   pitch = nx rounded up to a multiple of 8 (FP64), 16 (FP32) or 32 (16-bit
+ *   modes) elements;
+ *   phi[s]: nz*ny*pitch elements, FP64 in LBM_FP64 else FP32; node (x, y, z)
+ *     at (z*ny + y)*pitch + x;
+ *   mom[s]: nz*nmom*ny*pitch elements, FP64 / FP32 / IEEE binary16 / bfloat16
+ *     by precision; moment k of node (x, y, z) at ((z*nmom + k)*ny + y)*pitch + x,
+ *     k over P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz (nmom = 10), or P, J
+ *     (nmom = 4) with LBM_GRADIENT_CLOSURE; the 16-bit modes store
+ *     (value - enc_offset[k]) * enc_scale[k].
+ *   Elements x >= nx of a row are never read or written.
+ * enc_offset, enc_scale: 10 values each (rules of lbm_set_encoding) or both
+ *   NULL (the default encoding); ignored outside the 16-bit modes.
+ * parity: the buffer holding the current state; after the call the state is
+ *   in buffer parity ^ (nsteps & 1), and every node of it is written.
+ * stream: the hipStream_t the work is enqueued on (NULL: the null stream).
+ *   Asynchronous; no synchronisation.
+ * All argument checks run before any device call; errors are reported by
+ * lbm_last_error(NULL).  Every call on one GPU shares that GPU's descriptor
+ * and tile list, rewritten by each call: calls whose work overlaps on one GPU
+ * (different streams, or host threads) race and must be serialised. */
+lbm_status lbm_step_noalloc(const lbm_params* box, const lbm_tuning* tuning, void* const phi[2],
+                            void* const mom[2], const double* enc_offset, const double* enc_scale,
+                            int32_t parity, int32_t nsteps, void* stream);
+
 /* Release every device resource of the context.  NULL is a no-op. */
 void lbm_destroy(lbm_ctx* ctx);
 

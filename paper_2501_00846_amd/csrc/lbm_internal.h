@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "lbm.h"
+
 namespace lbm {
 
 constexpr int kFields = 11;  // phi, P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
@@ -80,6 +82,23 @@ hipError_t launch_gather(int precision, const BoxDesc& box, int parity, const in
 // Observable `which` (0 rho, 1 ux, 2 uy, 3 uz, 4 phi, 5 p) into N doubles.
 hipError_t launch_observable(int precision, const BoxDesc& box, int parity, int which,
                              double* d_dst, hipStream_t stream);
+
+// Host-side helpers shared by the context API (runtime.cpp) and the entry
+// point that allocates nothing (noalloc.hip).
+// Parameter checks of lbm_create for box idx; on failure the message is the
+// context-free error text (lbm_last_error(NULL)).
+lbm_status check_params(const lbm_params& p, int idx, int precision0, const char* who);
+// Set / clear the context-free error text; set_error returns s.
+lbm_status set_error(lbm_status s, const char* fmt, ...);
+void clear_error();
+// -1 if every scale is a positive power of two and every offset finite;
+// else k (scale[k] bad) or 10 + k (offset[k] bad).
+int check_encoding(const double* offset, const double* scale);
+// Offsets 0 and scales 1024 (P), 4096 (J), 65536 (Q).
+void default_encoding(double off[10], double scale[10]);
+// Descriptor of one box from its parameters; d.phi and d.mom must already
+// hold the state buffers (their alignment decides d.whole_rows).
+void fill_box_desc(const lbm_params& p, int precision, const double off[10], const double scale[10], BoxDesc& d);
 
 constexpr int kDiagValues = 28;
 constexpr int kDiagBlocks = 1024;

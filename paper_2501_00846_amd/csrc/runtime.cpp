@@ -100,8 +100,7 @@ bool finite(double v) { return std::isfinite(v); }
 
 int nmom_of(const lbm_params& p) { return (p.flags & LBM_GRADIENT_CLOSURE) ? 4 : 10; }
 
-lbm_status validate_box(const lbm_params& p, int idx, int precision0) {
-  const char* who = "lbm_create";
+lbm_status validate_box(const lbm_params& p, int idx, int precision0, const char* who = "lbm_create") {
   if (p.lattice != LBM_D3Q27) return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: lattice %d unsupported (D3Q27 only)", who, idx, p.lattice);
   if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: dims must be >= 1", who, idx);
   if (p.nx > (1 << 20) || p.ny > (1 << 20) || p.nz > (1 << 20)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: dims must be <= 2^20", who, idx);
@@ -124,46 +123,9 @@ lbm_status validate_box(const lbm_params& p, int idx, int precision0) {
   return LBM_OK;
 }
 
-void fill_desc(Box& b, int precision) {
-  const lbm_params& p = b.prm;
-  BoxDesc& d = b.desc;
-  d.nx = p.nx;
-  d.ny = p.ny;
-  d.nz = p.nz;
-  for (int a = 0; a < 3; ++a) d.wall[a] = p.bc[a] == LBM_WALL ? 1 : 0;
-  d.flags = p.flags;
-  d.nmom = nmom_of(p);
-  d.rho_g = p.rho_g;
-  d.drho = p.rho_l - p.rho_g;
-  d.nu_g = p.nu_g;
-  d.dnu = p.nu_l - p.nu_g;
-  d.beta4 = 4.0 * 12.0 * p.sigma / p.width;
-  d.kappa_mu = 1.5 * p.sigma * p.width;
-  d.mobility = p.mobility;
-  d.kappa_ac = 4.0 * p.mobility / p.width;
-  for (int a = 0; a < 3; ++a) d.grav[a] = p.gravity[a];
-  d.rho_ref = p.rho_ref;
-  d.pitch = lbm::row_pitch(precision, p.nx);
-  bool rows = true;  // rows of pitch elements are whole 64-byte multiples
-  for (int s = 0; s < 2; ++s)
-    rows = rows && reinterpret_cast<uintptr_t>(d.phi[s]) % 64 == 0 && reinterpret_cast<uintptr_t>(d.mom[s]) % 64 == 0;
-  d.whole_rows = rows ? 1 : 0;
-  const bool os = precision == LBM_FP16_OS || precision == LBM_BF16_OS;
-  for (int k = 0; k < 10; ++k) {
-    d.enc_off[k] = os ? static_cast<float>(b.enc_off[k]) : 0.f;
-    d.enc_scale[k] = os ? static_cast<float>(b.enc_scale[k]) : 1.f;
-    d.enc_inv[k] = os ? static_cast<float>(1.0 / b.enc_scale[k]) : 1.f;
-  }
-}
+void fill_desc(Box& b, int precision) { lbm::fill_box_desc(b.prm, precision, b.enc_off, b.enc_scale, b.desc); }
 
-void default_encoding(Box& b) {
-  // stored = (v - off) * scale: typical magnitudes land near 2^10 in FP16
-  const double sP = 1024.0, sJ = 4096.0, sQ = 65536.0;
-  for (int k = 0; k < 10; ++k) b.enc_off[k] = 0.0;
-  b.enc_scale[0] = sP;
-  for (int k = 1; k < 4; ++k) b.enc_scale[k] = sJ;
-  for (int k = 4; k < 10; ++k) b.enc_scale[k] = sQ;
-}
+void default_encoding(Box& b) { lbm::default_encoding(b.enc_off, b.enc_scale); }
 
 void drop_graphs(lbm_ctx* c) {
   for (auto& kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
@@ -321,6 +283,76 @@ int wave_balanced_chunk(const lbm_ctx* c, int tx, int ty, int64_t slots, int max
 }
 
 }  // namespace
+
+// Shared with the entry point that allocates nothing (noalloc.hip).
+namespace lbm {
+
+lbm_status check_params(const lbm_params& p, int idx, int precision0, const char* who) {
+  return validate_box(p, idx, precision0, who);
+}
+
+lbm_status set_error(lbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_create_error = buf;
+  return s;
+}
+
+void clear_error() { g_create_error.clear(); }
+
+int check_encoding(const double* offset, const double* scale) {
+  for (int k = 0; k < 10; ++k) {
+    int ex = 0;
+    const double m = std::frexp(scale[k], &ex);
+    if (!(std::isfinite(scale[k]) && scale[k] > 0 && m == 0.5)) return k;
+    if (!std::isfinite(offset[k])) return 10 + k;
+  }
+  return -1;
+}
+
+void default_encoding(double off[10], double scale[10]) {
+  // stored = (v - off) * scale: typical magnitudes land near 2^10 in FP16
+  const double sP = 1024.0, sJ = 4096.0, sQ = 65536.0;
+  for (int k = 0; k < 10; ++k) off[k] = 0.0;
+  scale[0] = sP;
+  for (int k = 1; k < 4; ++k) scale[k] = sJ;
+  for (int k = 4; k < 10; ++k) scale[k] = sQ;
+}
+
+void fill_box_desc(const lbm_params& p, int precision, const double off[10], const double scale[10], BoxDesc& d) {
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.nz = p.nz;
+  for (int a = 0; a < 3; ++a) d.wall[a] = p.bc[a] == LBM_WALL ? 1 : 0;
+  d.flags = p.flags;
+  d.nmom = nmom_of(p);
+  d.rho_g = p.rho_g;
+  d.drho = p.rho_l - p.rho_g;
+  d.nu_g = p.nu_g;
+  d.dnu = p.nu_l - p.nu_g;
+  d.beta4 = 4.0 * 12.0 * p.sigma / p.width;
+  d.kappa_mu = 1.5 * p.sigma * p.width;
+  d.mobility = p.mobility;
+  d.kappa_ac = 4.0 * p.mobility / p.width;
+  for (int a = 0; a < 3; ++a) d.grav[a] = p.gravity[a];
+  d.rho_ref = p.rho_ref;
+  d.pitch = row_pitch(precision, p.nx);
+  bool rows = true;  // rows of pitch elements are whole 64-byte multiples
+  for (int s = 0; s < 2; ++s)
+    rows = rows && reinterpret_cast<uintptr_t>(d.phi[s]) % 64 == 0 && reinterpret_cast<uintptr_t>(d.mom[s]) % 64 == 0;
+  d.whole_rows = rows ? 1 : 0;
+  const bool os = precision == LBM_FP16_OS || precision == LBM_BF16_OS;
+  for (int k = 0; k < 10; ++k) {
+    d.enc_off[k] = os ? static_cast<float>(off[k]) : 0.f;
+    d.enc_scale[k] = os ? static_cast<float>(scale[k]) : 1.f;
+    d.enc_inv[k] = os ? static_cast<float>(1.0 / scale[k]) : 1.f;
+  }
+}
+
+}  // namespace lbm
 
 extern "C" {
 
@@ -571,12 +603,9 @@ lbm_status lbm_set_encoding(lbm_ctx* c, int32_t box, const double* offset, const
   lbm_status s = check_box(c, box);
   if (s != LBM_OK) return s;
   if (!offset || !scale) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: NULL offset/scale");
-  for (int k = 0; k < 10; ++k) {
-    int ex = 0;
-    const double m = std::frexp(scale[k], &ex);
-    if (!(std::isfinite(scale[k]) && scale[k] > 0 && m == 0.5)) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: scale[%d] must be a positive power of two", k);
-    if (!std::isfinite(offset[k])) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: offset[%d] must be finite", k);
-  }
+  const int bad = lbm::check_encoding(offset, scale);
+  if (bad >= 10) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: offset[%d] must be finite", bad - 10);
+  if (bad >= 0) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: scale[%d] must be a positive power of two", bad);
   Box& b = c->boxes[box];
   if (c->precision != LBM_FP16_OS && c->precision != LBM_BF16_OS) return LBM_OK;
   const BoxDesc before = b.desc;

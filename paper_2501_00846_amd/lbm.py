@@ -95,6 +95,9 @@ _SIGS = {
     "lbm_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
     "lbm_bytes_per_update": (ctypes.c_double, [ctypes.c_void_p]),
     "lbm_total_nodes": (ctypes.c_int64, [ctypes.c_void_p]),
+    "lbm_step_noalloc": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(lbm_tuning),
+                                        ctypes.c_void_p * 2, ctypes.c_void_p * 2, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "lbm_destroy": (None, [ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
@@ -252,6 +255,30 @@ def lbm_bytes_per_update(ctx):
 
 def lbm_total_nodes(ctx):
     return load_library().lbm_total_nodes(ctx)
+
+
+def lbm_step_noalloc(params, tuning, phi, mom, enc_offset=None, enc_scale=None, parity=0, nsteps=1,
+                     stream=None):
+    """params: lbm_params; tuning: lbm_tuning or None; phi, mom: two device
+    addresses each (the caller's ping-pong buffers); stream: a hipStream_t
+    handle (int) or None."""
+    off = None if enc_offset is None else _f64(enc_offset, 10)
+    sc = None if enc_scale is None else _f64(enc_scale, 10)
+    ph = (ctypes.c_void_p * 2)(*[int(v) for v in phi])
+    mo = (ctypes.c_void_p * 2)(*[int(v) for v in mom])
+    _check(load_library().lbm_step_noalloc(ctypes.byref(params), None if tuning is None else ctypes.byref(tuning),
+                                           ph, mo, _ptr(off), _ptr(sc), int(parity), int(nsteps),
+                                           None if stream is None else ctypes.c_void_p(int(stream))))
+
+
+def row_pitch(precision, nx):
+    """Stored row length (elements) of the device layout: nx rounded up so that
+    rows of phi and of every moment field start on 64-byte boundaries (the
+    layout lbm_step_noalloc documents)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    e = 8 if prec == 0 else (4 if prec == 1 else 2)
+    q = 64 // e
+    return (nx + q - 1) // q * q
 
 
 def lbm_destroy(ctx):

@@ -110,3 +110,57 @@ def test_create_rejects_oversized_boxes():
     assert st == -1 and "2^20" in msg
     st, _, msg = _create([_params(nx=16385, ny=16384, nz=1)])
     assert st == -1 and "2^28" in msg
+
+
+def _noalloc(params, tuning=None, phi=(0x10000, 0x20000), mom=(0x30000, 0x40000), off=None, sc=None,
+             parity=0, nsteps=0):
+    lib = lbm.load_library()
+    ph = (ctypes.c_void_p * 2)(*phi)
+    mo = (ctypes.c_void_p * 2)(*mom)
+    offa = None if off is None else (ctypes.c_double * 10)(*off)
+    sca = None if sc is None else (ctypes.c_double * 10)(*sc)
+    st = lib.lbm_step_noalloc(ctypes.byref(params) if params is not None else None,
+                              ctypes.byref(tuning) if tuning is not None else None,
+                              ph, mo, ctypes.cast(offa, ctypes.c_void_p) if offa else None,
+                              ctypes.cast(sca, ctypes.c_void_p) if sca else None, parity, nsteps, None)
+    return st, lbm.lbm_last_error(None)
+
+
+def test_noalloc_step_checks_arguments_before_any_device_call():
+    """The entry point that allocates nothing validates everything on the
+    host: with valid arguments and nsteps = 0 it returns LBM_OK without a
+    device (none exists here); every bad argument is rejected with its code."""
+    assert _noalloc(_params())[0] == 0
+    assert _noalloc(_params(precision=2), off=[0.0] * 10, sc=[1024.0] * 10)[0] == 0
+    st, msg = _noalloc(None)
+    assert st == -1 and "NULL" in msg
+    st, msg = _noalloc(_params(nx=0))
+    assert st == -1 and "dims" in msg
+    st, msg = _noalloc(_params(), phi=(0x10000, 0))
+    assert st == -1 and "NULL" in msg
+    st, msg = _noalloc(_params(), mom=(0x30004, 0x40000))  # FP64 moments need 8-byte alignment
+    assert st == -1 and "aligned" in msg
+    st, msg = _noalloc(_params(), parity=2)
+    assert st == -1 and "parity" in msg
+    st, msg = _noalloc(_params(), nsteps=-1)
+    assert st == -1 and "nsteps" in msg
+    st, msg = _noalloc(_params(precision=2), off=[0.0] * 10)
+    assert st == -1 and "together" in msg
+    st, msg = _noalloc(_params(precision=2), off=[0.0] * 10, sc=[1000.0] * 10)
+    assert st == -1 and "power of two" in msg
+    st, msg = _noalloc(_params(precision=2), off=[float("inf")] + [0.0] * 9, sc=[1024.0] * 10)
+    assert st == -1 and "finite" in msg
+    st, msg = _noalloc(_params(), tuning=lbm.lbm_tuning(33, 8, 4, 0))
+    assert st == -2 and "unsupported" in msg
+    st, msg = _noalloc(_params(), tuning=lbm.lbm_tuning(34, 8, 0, 0))
+    assert st == -1 and "z_chunk" in msg
+
+
+def test_noalloc_step_rejects_tile_lists_beyond_its_static_scratch():
+    """1 MiB of scratch holds 32,736 tiles: a 512^3 box with 32 x 13 output
+    columns per tile (640 tiles per z-chunk) fits from z-chunk 11 up."""
+    big = _params(nx=512, ny=512, nz=512)
+    assert _noalloc(big, tuning=lbm.lbm_tuning(34, 15, 11, 0))[0] == 0
+    st, msg = _noalloc(big, tuning=lbm.lbm_tuning(34, 15, 10, 0))
+    assert st == -1 and "scratch" in msg and "33280" in msg
+    assert _noalloc(big)[0] == 0  # the default z-chunk fits
