@@ -236,6 +236,13 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None
     nodes = ctx.total_nodes
     bpl = ctx.bytes_per_update
     diag = ctx.diagnostics(0)
+    # cost of the FP64 reductions of every box (one launch, synchronised):
+    # best of three calls
+    diag_ms = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        ctx.diagnostics_all()
+        diag_ms.append((time.perf_counter() - t1) * 1e3)
     tuning = ctx.tuning()
     obs = ctx.fields(0) if fields else None
     ctx.close()
@@ -246,7 +253,7 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None
                 kernel_ms_median=float(np.median(seg_ms)), nodes=nodes,
                 bytes_per_update=bpl, achieved_gbs=achieved, frac=achieved / PEAK_HBM_GBS,
                 tuning=tuning, phase_mass=diag["phase_mass"], nonfinite=diag["nonfinite"],
-                fields=obs)
+                diagnostics_ms=min(diag_ms), fields=obs)
 
 
 def field_errors(got, ref):
@@ -522,6 +529,8 @@ def main():
     ap.add_argument("--closure", default="moment", choices=["moment", "gradient"],
                     help="a2 from the stored second moment (the paper's algorithm) or from the "
                          "velocity gradient (5-field state)")
+    ap.add_argument("--high-order", action="store_true",
+                    help="fourth-order phase-field update (the flow solver keeps its stencils)")
     ap.add_argument("--tuning", default=None, metavar="BX,BY,ZCHUNK,PERSISTENT",
                     help="fixed launch configuration instead of autotuning")
     args = ap.parse_args()
@@ -557,7 +566,11 @@ def main():
         for c in cases:
             c.problem.gradient_closure = True
         desc += ", gradient closure (state phi, P, J)"
-    cfg_key = args.config + ("/gc" if gc else "")
+    if args.high_order:
+        for c in cases:
+            c.problem.high_order_ac = True
+        desc += ", fourth-order phase-field update"
+    cfg_key = args.config + ("/gc" if gc else "") + ("/ho" if args.high_order else "")
     problems = [c.problem for c in cases]
     # per-field error against the FP64 run: only for single-box workloads
     # that run FP64 among their modes
@@ -617,7 +630,8 @@ def main():
     roof.update({"traffic": traffic, "copy_gbs": round(copy_gbs, 1),
                  "frac_of_copy": round(m["achieved_gbs"] / copy_gbs, 4),
                  "hbm_floor_ms": round(hbm_floor_ms, 4), "alu": alu,
-                 "kernel": "fused_step (%s)" % head, "kernel_ms": round(m["kernel_ms"], 4),
+                 "kernel": "fused_step (%s)" % head + (" + ho_flux + ho_phase" if args.high_order else ""),
+                 "kernel_ms": round(m["kernel_ms"], 4),
                  "bytes_per_update": m["bytes_per_update"], "nodes_per_launch": m["nodes"]})
     cpu = None
     if not args.no_cpu:
@@ -637,7 +651,8 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[head],
         "data": "synthetic (seeded initial droplet/bubble fields)",
-        "config": {"workload": desc, "config": args.config, "closure": args.closure, "nodes": m["nodes"],
+        "config": {"workload": desc, "config": args.config, "closure": args.closure,
+                   "phase_update": "fourth-order" if args.high_order else "second-order", "nodes": m["nodes"],
                    "precision": head, "tuning": m["tuning"], "steps_per_launch": 1},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -647,6 +662,7 @@ def main():
                       "achieved_gbs": round(v["achieved_gbs"], 1), "frac": round(v["frac"], 4),
                       "bytes_per_update": v["bytes_per_update"], "tuning": v["tuning"],
                       "alu": v.get("alu"), "error_vs_fp64": v.get("error_vs_fp64"),
+                      "diagnostics_ms": round(v["diagnostics_ms"], 3),
                       "nonfinite": v["nonfinite"]} for p, v in modes.items()},
         "paper_context": PAPER_CONTEXT,
     }

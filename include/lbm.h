@@ -85,7 +85,17 @@ enum {
    * The state is then phi, P, J only: 5 stored fields per node instead of
    * 11, and the Q fields of lbm_get_state read 0 (lbm_set_state ignores
    * them).  All boxes of a context must agree on this flag. */
-  LBM_GRADIENT_CLOSURE = 2
+  LBM_GRADIENT_CLOSURE = 2,
+  /* Fourth-order phase-field update: the divergence, Laplacian and normal
+   * gradient of the Allen-Cahn FTCS update become (4 D1 - D2)/3, the
+   * isotropic D3Q27 stencil at spacings 1 and 2 (the higher-order
+   * discretisation named as future work at the end of Sec. II.A; the flow
+   * solver keeps the second-order stencils of Sec. II.C).  Wall axes need
+   * at least 4 nodes.  Each step then also keeps 6 doubles per node of
+   * device memory (velocity and sharpening flux of level n) and runs two
+   * more kernels.  All boxes of a context must agree on this flag; not
+   * available through lbm_step_noalloc. */
+  LBM_HIGH_ORDER_AC = 4
 };
 
 /* One box.  phi = 1 is the liquid (subscript l), phi = 0 the gas (g). */
@@ -95,7 +105,7 @@ typedef struct {
   int32_t lattice;        /* lbm_lattice */
   int32_t bc[3];          /* lbm_bc per axis x, y, z */
   int32_t precision;      /* lbm_precision; identical for all boxes of a context */
-  int32_t flags;          /* LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE, or 0 */
+  int32_t flags;          /* LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE | LBM_HIGH_ORDER_AC, or 0 */
   double rho_l, rho_g;    /* phase densities, > 0 (Sec. II.C) */
   double nu_l, nu_g;      /* kinematic viscosities, > 0; omega = 1/(3 nu + 1/2) */
   double sigma;           /* surface tension, >= 0 (Sec. II.C: beta = 12 sigma/W, kappa = 3 sigma W/2) */
@@ -191,6 +201,13 @@ lbm_status lbm_get_fields(lbm_ctx* ctx, int32_t box, double* rho, double* u, dou
  * Eq. press_corr) from which the Laplace jump is read.  *out is written
  * whenever the reduction ran.  Synchronises; LBM_ERR_UNSTABLE if nonfinite. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, int32_t box, lbm_diag* out);
+
+/* The reductions of lbm_diagnostics for every box of the context from one
+ * launch (an ensemble's observables at the cost of one call): out holds
+ * n_boxes structs, box after box, each bitwise equal to what
+ * lbm_diagnostics returns for that box.  Synchronises; LBM_ERR_UNSTABLE
+ * (every struct written) if any box holds a non-finite value. */
+lbm_status lbm_diagnostics_all(lbm_ctx* ctx, lbm_diag* out);
 
 /* Raw state of one box as 11 N-double planes in the order
  * phi, P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz (decoded to FP64).

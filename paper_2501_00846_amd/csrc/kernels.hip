@@ -1086,15 +1086,31 @@ __global__ void __launch_bounds__(256) observable_kernel(BoxDesc b, int parity, 
 //  17-19 sum (1-phi) u | 20 sum p (phi>=0.98) | 21 count | 22 sum p (phi<=0.02)
 //  23 count | 24 nonfinite flag | 25-27 unused
 constexpr int kDiagThreads = 256;
+constexpr int kDiagWaves = kDiagThreads / 64;
 
 __device__ inline double combine(int k, double a, double b) {
   if (k == 6 || k == 24) return a > b ? a : b;
   return a + b;
 }
 
+// Sum (max for the max-type values) over the 64 lanes of a wavefront by a
+// butterfly of lane exchanges; lane 0 ends with the values combined in a fixed
+// order, so the result does not depend on scheduling.
+__device__ __forceinline__ double wave_combine(int k, double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = combine(k, v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// One launch covers boxes box0 .. box0 + gridDim.y - 1 of the descriptor
+// array; gridDim.x workgroups share each box (grid-stride over its nodes) and
+// write one partial per value: partials[(blockIdx.y * gridDim.x + blockIdx.x)
+// * kDiagValues + k].
 template <class PR>
-__global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(BoxDesc b, int parity, double* __restrict__ partials) {
-  __shared__ double red[kDiagThreads];
+__global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity,
+                                                                    double* __restrict__ partials) {
+  __shared__ double red[kDiagWaves][kDiagValues];
+  const BoxDesc& b = boxes[box0 + blockIdx.y];
   double acc[kDiagValues];
   for (int k = 0; k < kDiagValues; ++k) acc[k] = 0.0;
   const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
@@ -1123,35 +1139,158 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(BoxDesc b, i
     if (phi <= 0.02) { acc[22] += p; acc[23] += 1.0; }
     if (!fin) acc[24] = 1.0;
   }
-  // block reduction, fixed order (unrolled: a runtime index into acc would
-  // move the accumulators from registers to scratch memory)
+  // wavefront reductions (unrolled: a runtime index into acc would move the
+  // accumulators from registers to scratch memory), then the waves of the
+  // workgroup in order through LDS
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < kDiagValues; ++k) {
-    red[threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] = combine(k, red[threadIdx.x], red[threadIdx.x + s]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[blockIdx.x * kDiagValues + k] = red[0];
-    __syncthreads();
+    const double v = wave_combine(k, acc[k]);
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDiagValues) {
+    const int k = threadIdx.x;
+    double v = red[0][k];
+    for (int w = 1; w < kDiagWaves; ++w) v = combine(k, v, red[w][k]);
+    partials[(static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * kDiagValues + k] = v;
   }
 }
 
+// One workgroup per box: each wave takes values k = wave, wave + 4, ...; its
+// lanes combine the box's nblocks partials in a fixed stride order, then the
+// lanes by a wavefront reduction.  out[box * kDiagValues + k].
 __global__ void __launch_bounds__(kDiagThreads) diag_final_kernel(const double* __restrict__ partials, int nblocks,
                                                                   double* __restrict__ out) {
-  __shared__ double red[kDiagThreads];
-  for (int k = 0; k < kDiagValues; ++k) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += kDiagThreads) a = combine(k, a, partials[i * kDiagValues + k]);
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] = combine(k, red[threadIdx.x], red[threadIdx.x + s]);
-      __syncthreads();
+  const double* p = partials + static_cast<int64_t>(blockIdx.x) * nblocks * kDiagValues;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = wave; k < kDiagValues; k += kDiagWaves) {
+    double a = 0.0;  // identity of both the sums and the maxima (|u| and the flag are >= 0)
+    for (int i = lane; i < nblocks; i += 64) a = combine(k, a, p[static_cast<int64_t>(i) * kDiagValues + k]);
+    a = wave_combine(k, a);
+    if (lane == 0) out[blockIdx.x * kDiagValues + k] = a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fourth-order phase-field update (LBM_HIGH_ORDER_AC)
+// ---------------------------------------------------------------------------
+// The higher-order discretisation that Sec. II.A names as future work, with
+// no scheme given there: the divergence, the Laplacian and the gradient
+// inside the normal of the FTCS update are the Richardson combination
+// (4 D1 - D2) / 3 of the isotropic D3Q27 stencil at spacing 1 (D1, neighbours
+// x + c) and at spacing 2 (D2, neighbours x + 2c, the first derivative
+// divided by 2, the Laplacian by 4).  The leading errors of D1 and D2 are
+// isotropic and in the ratio 1 : 4, so the combination removes them.  The
+// flow solver keeps the second-order stencils (the fused step is unchanged;
+// its phi output is overwritten).  Two kernels, both reading level n:
+//   ho_flux_kernel  per node: u = J + a/2 with the forces of Sec. II.C
+//                   (node_obs, FP64) and S = phi (1 - phi) n4, n4 the unit
+//                   fourth-order gradient; 6 doubles into b.aux;
+//   ho_phase_kernel per node: phi' = phi - div4(phi u) + M lap4(phi)
+//                   - (4M/W) div4(S), or u . grad4(phi) for the printed
+//                   advection.  Neighbours beyond a wall are mirrored nodes,
+//                   with u negated per crossed wall and the crossed
+//                   components of S negated (the normal of the mirrored phi).
+
+// phi of node (x, y, z), coordinates already inside the box
+template <class PR>
+__device__ __forceinline__ double phi_node(const BoxDesc& b, int parity, int x, int y, int z) {
+  using TP = typename PR::TP;
+  return dec<double>(((gptr<const TP>)b.phi[parity])[phi_at(b, x, y, z)], 0.f, 1.f);
+}
+
+template <class PR>
+__global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
+  const BoxDesc& b = boxes[box0 + blockIdx.y];
+  const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
+  double* aux = b.aux;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int x, y, z;
+    node_xyz(b, i, x, y, z);
+    double rho, u[3], phi, p, ps;
+    bool fin;
+    node_obs<PR>(b, parity, x, y, z, rho, u, phi, p, ps, fin);
+    double g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
+    for (int cz = -1; cz <= 1; ++cz)
+      for (int cy = -1; cy <= 1; ++cy)
+        for (int cx = -1; cx <= 1; ++cx) {
+          if (cx == 0 && cy == 0 && cz == 0) continue;
+          const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
+          const double v1 = phi_node<PR>(b, parity, map_axis(x + cx, b.nx, b.wall[0]), map_axis(y + cy, b.ny, b.wall[1]),
+                                         map_axis(z + cz, b.nz, b.wall[2]));
+          const double v2 = phi_node<PR>(b, parity, map_axis(x + 2 * cx, b.nx, b.wall[0]),
+                                         map_axis(y + 2 * cy, b.ny, b.wall[1]), map_axis(z + 2 * cz, b.nz, b.wall[2]));
+          const double c[3] = {double(cx), double(cy), double(cz)};
+          for (int a = 0; a < 3; ++a) {
+            g1[a] += 3.0 * w * c[a] * v1;
+            g2[a] += 1.5 * w * c[a] * v2;
+          }
+        }
+    double g[3];
+    for (int a = 0; a < 3; ++a) g[a] = (4.0 * g1[a] - g2[a]) / 3.0;
+    const double inv = 1.0 / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + 1e-12);
+    const double pp = phi * (1.0 - phi);
+    for (int a = 0; a < 3; ++a) {
+      aux[a * n + i] = u[a];
+      aux[(3 + a) * n + i] = pp * g[a] * inv;
     }
-    if (threadIdx.x == 0) out[k] = red[0];
-    __syncthreads();
+  }
+}
+
+template <class PR>
+__global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
+  using TP = typename PR::TP;
+  const BoxDesc& b = boxes[box0 + blockIdx.y];
+  const int nx = b.nx, ny = b.ny, nz = b.nz;
+  const int64_t n = static_cast<int64_t>(nx) * ny * nz;
+  const double* aux = b.aux;
+  const bool literal = (b.flags & 1) != 0;
+  const double kac = b.kappa_ac, mob = b.mobility;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int x, y, z;
+    node_xyz(b, i, x, y, z);
+    const double phi0 = phi_node<PR>(b, parity, x, y, z);
+    double adv[2] = {0, 0}, shp[2] = {0, 0}, lap[2] = {0, 0}, g[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int cz = -1; cz <= 1; ++cz)
+      for (int cy = -1; cy <= 1; ++cy)
+        for (int cx = -1; cx <= 1; ++cx) {
+          if (cx == 0 && cy == 0 && cz == 0) continue;
+          const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
+          const double c[3] = {double(cx), double(cy), double(cz)};
+          for (int s = 1; s <= 2; ++s) {
+            int kx, ky, kz;
+            const int xm = map_axis(x + s * cx, nx, b.wall[0], kx);
+            const int ym = map_axis(y + s * cy, ny, b.wall[1], ky);
+            const int zm = map_axis(z + s * cz, nz, b.wall[2], kz);
+            const int64_t j = (static_cast<int64_t>(zm) * ny + ym) * nx + xm;
+            const double ph = phi_node<PR>(b, parity, xm, ym, zm);
+            const double su = ((kx + ky + kz) & 1) ? -1.0 : 1.0;
+            const double sn[3] = {kx ? -1.0 : 1.0, ky ? -1.0 : 1.0, kz ? -1.0 : 1.0};
+            double uc = 0, sc = 0;
+            for (int a = 0; a < 3; ++a) {
+              uc += c[a] * aux[a * n + j];
+              sc += c[a] * sn[a] * aux[(3 + a) * n + j];
+            }
+            const double wt = 3.0 * w / s;
+            adv[s - 1] += wt * ph * su * uc;
+            shp[s - 1] += wt * sc;
+            lap[s - 1] += (6.0 * w / (s * s)) * (ph - phi0);
+            for (int a = 0; a < 3; ++a) g[s - 1][a] += wt * c[a] * ph;
+          }
+        }
+    auto four = [](const double* v) { return (4.0 * v[0] - v[1]) / 3.0; };
+    double a_term;
+    if (literal) {
+      a_term = 0.0;
+      for (int a = 0; a < 3; ++a) a_term += aux[a * n + i] * (4.0 * g[0][a] - g[1][a]) / 3.0;
+    } else {
+      a_term = four(adv);
+    }
+    const double phin = phi0 - a_term + mob * four(lap) - kac * four(shp);
+    ((gptr<TP>)b.phi[1 - parity])[phi_at(b, x, y, z)] = Enc<TP>::go(phin, 0.f, 1.f);
   }
 }
 
@@ -1310,19 +1449,40 @@ hipError_t launch_observable(int precision, const BoxDesc& box, int parity, int 
   });
 }
 
-hipError_t launch_diagnostics(int precision, const BoxDesc& box, int parity, double* d_partials, double* d_out,
-                              hipStream_t stream) {
-  const int64_t n = static_cast<int64_t>(box.nx) * box.ny * box.nz;
-  int nb = grid_for(n, kDiagThreads);
-  if (nb > kDiagBlocks) nb = kDiagBlocks;
+int high_order_blocks_per_box(int64_t max_nodes) {
+  int64_t nb = (max_nodes + 256 * 4 - 1) / (256 * 4);
+  return static_cast<int>(nb < 1 ? 1 : (nb > 8192 ? 8192 : nb));
+}
+
+hipError_t launch_high_order_phase(int precision, const BoxDesc* d_boxes, int box0, int nbox, int parity,
+                                   int blocks_per_box, hipStream_t stream) {
+  if (nbox <= 0 || blocks_per_box <= 0) return hipErrorInvalidValue;
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((ho_flux_kernel<PR>), dim3(blocks_per_box, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ho_phase_kernel<PR>), dim3(blocks_per_box, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    return hipGetLastError();
+  });
+}
+
+int diag_blocks_per_box(int64_t max_nodes) {
+  int64_t nb = (max_nodes + kDiagThreads * 16 - 1) / (kDiagThreads * 16);
+  return static_cast<int>(nb < 1 ? 1 : (nb > kDiagBlocks ? kDiagBlocks : nb));
+}
+
+hipError_t launch_diagnostics(int precision, const BoxDesc* d_boxes, int box0, int nbox, int parity,
+                              int blocks_per_box, double* d_partials, double* d_out, hipStream_t stream) {
+  if (nbox <= 0 || blocks_per_box <= 0) return hipErrorInvalidValue;
   hipError_t e = dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
-    hipLaunchKernelGGL((diag_partial_kernel<PR>), dim3(nb), dim3(kDiagThreads), 0, stream, box, parity,
-                       d_partials);
+    hipLaunchKernelGGL((diag_partial_kernel<PR>), dim3(blocks_per_box, nbox), dim3(kDiagThreads), 0, stream, d_boxes,
+                       box0, parity, d_partials);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagThreads), 0, stream, d_partials, nb, d_out);
+  hipLaunchKernelGGL(diag_final_kernel, dim3(nbox), dim3(kDiagThreads), 0, stream, d_partials, blocks_per_box, d_out);
   return hipGetLastError();
 }
 

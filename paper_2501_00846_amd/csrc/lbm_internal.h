@@ -25,7 +25,7 @@ struct BoxDesc {
   void* mom[2];
   int32_t nx, ny, nz;
   int32_t wall[3];        // 1 if the axis has walls
-  int32_t flags;          // LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE
+  int32_t flags;          // LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE | LBM_HIGH_ORDER_AC
   int32_t nmom;           // moment fields stored per node: 10, or 4 (gradient closure)
   double rho_g, drho;     // rho = rho_g + phi * drho
   double nu_g, dnu;       // nu = nu_g + phi * dnu
@@ -42,6 +42,8 @@ struct BoxDesc {
                           // (buffer bases multiples of 64 bytes)
   int32_t pitch;          // elements from one stored row to the next (>= nx; the
                           // padding after column nx-1 is never read or written)
+  double* aux;            // LBM_HIGH_ORDER_AC: 6 compact planes of nx*ny*nz doubles
+                          // (u, then phi (1 - phi) n4) of the step's level n; else NULL
 };
 
 // One unit of work of the fused step: an output tile (x0, y0) of one box,
@@ -100,11 +102,25 @@ void default_encoding(double off[10], double scale[10]);
 // hold the state buffers (their alignment decides d.whole_rows).
 void fill_box_desc(const lbm_params& p, int precision, const double off[10], const double scale[10], BoxDesc& d);
 
+// Fourth-order phase-field update of boxes box0 .. box0 + nbox - 1 (every
+// one with LBM_HIGH_ORDER_AC and its aux planes): reads state `parity`,
+// overwrites phi of buffer 1 - parity.  Runs after the fused step of the same
+// parity; blocks_per_box workgroups share each box.
+hipError_t launch_high_order_phase(int precision, const BoxDesc* d_boxes, int box0, int nbox, int parity,
+                                   int blocks_per_box, hipStream_t stream);
+int high_order_blocks_per_box(int64_t max_nodes);
+
 constexpr int kDiagValues = 28;
 constexpr int kDiagBlocks = 1024;
-// FP64 reductions of one box: partials (kDiagBlocks * kDiagValues doubles),
-// then the final kDiagValues doubles into d_out (deterministic order).
-hipError_t launch_diagnostics(int precision, const BoxDesc& box, int parity, double* d_partials,
-                              double* d_out, hipStream_t stream);
+// Workgroups per box of the diagnostics launch for boxes of at most
+// max_nodes nodes (at least 16 nodes per thread, at most kDiagBlocks).
+int diag_blocks_per_box(int64_t max_nodes);
+// FP64 reductions of boxes box0 .. box0 + nbox - 1 of the device descriptor
+// array in one launch: partials (nbox * blocks_per_box * kDiagValues
+// doubles), then kDiagValues doubles per box into d_out (box after box).  The
+// order of every sum is fixed by blocks_per_box alone, so a box gives bitwise
+// the same values whether it is reduced alone or with the others.
+hipError_t launch_diagnostics(int precision, const BoxDesc* d_boxes, int box0, int nbox, int parity,
+                              int blocks_per_box, double* d_partials, double* d_out, hipStream_t stream);
 
 }  // namespace lbm

@@ -31,6 +31,7 @@ struct Box {
   lbm_params prm{};
   BoxDesc desc{};
   void* mem[2] = {nullptr, nullptr};
+  void* aux = nullptr;  // LBM_HIGH_ORDER_AC: 6 planes of n doubles
   int64_t n = 0;
   bool initialized = false;
   double enc_off[10] = {0};
@@ -43,6 +44,8 @@ struct lbm_ctx {
   std::vector<Box> boxes;
   int precision = 0;
   bool gc = false;  // LBM_GRADIENT_CLOSURE (all boxes)
+  bool ho = false;  // LBM_HIGH_ORDER_AC (all boxes)
+  int ho_bpb = 1;   // workgroups per box of the fourth-order phase kernels
   hipStream_t stream = nullptr;
   bool own_stream = false;
   lbm_device dev{};
@@ -56,7 +59,8 @@ struct lbm_ctx {
   std::map<std::pair<int, int>, hipGraphExec_t> graph_cache;  // (steps, parity)
   double* d_stage = nullptr;
   int64_t stage_n = 0;
-  double* d_diag = nullptr;  // partials + final
+  double* d_diag = nullptr;  // diagnostics partials (n_boxes * diag_bpb values) + one result per box
+  int diag_bpb = 1;          // diagnostics workgroups per box
   std::string err;
   int device = 0;
 };
@@ -113,7 +117,10 @@ lbm_status validate_box(const lbm_params& p, int idx, int precision0, const char
   }
   if (p.precision < LBM_FP64 || p.precision > LBM_BF16_OS) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: precision %d invalid", who, idx, p.precision);
   if (p.precision != precision0) return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: all boxes of a context must share one precision", who, idx);
-  if (p.flags & ~(LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: unknown flags 0x%x", who, idx, p.flags);
+  if (p.flags & ~(LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE | LBM_HIGH_ORDER_AC)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: unknown flags 0x%x", who, idx, p.flags);
+  if (p.flags & LBM_HIGH_ORDER_AC)
+    for (int a = 0; a < 3; ++a)
+      if (p.bc[a] == LBM_WALL && d[a] < 4) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: wall axis %d needs >= 4 nodes with LBM_HIGH_ORDER_AC", who, idx, a);
   if (!(finite(p.rho_l) && p.rho_l > 0 && finite(p.rho_g) && p.rho_g > 0)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: densities must be finite and > 0", who, idx);
   if (!(finite(p.nu_l) && p.nu_l > 0 && finite(p.nu_g) && p.nu_g > 0)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: viscosities must be finite and > 0 (tau > 1/2)", who, idx);
   if (!(finite(p.sigma) && p.sigma >= 0)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: sigma must be finite and >= 0", who, idx);
@@ -208,6 +215,11 @@ hipError_t enqueue_steps(lbm_ctx* c, int nsteps, int parity0) {
     hipError_t e = lbm::launch_fused(c->precision, c->gc, c->tuning.block_x, c->tuning.block_y, c->d_boxes,
                                      c->d_items, c->n_items, grid, parity, c->stream);
     if (e != hipSuccess) return e;
+    if (c->ho) {
+      e = lbm::launch_high_order_phase(c->precision, c->d_boxes, 0, static_cast<int>(c->boxes.size()), parity,
+                                       c->ho_bpb, c->stream);
+      if (e != hipSuccess) return e;
+    }
     parity ^= 1;
   }
   return hipSuccess;
@@ -264,6 +276,30 @@ bool all_finite(const double* v, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
   return true;
+}
+
+// lbm_diag from the kDiagValues reduced values of one box; true if the box
+// holds a non-finite value.
+bool fill_diag(const double* v, lbm_diag* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->phase_mass = v[0];
+  out->pstar_sum = v[1];
+  for (int a = 0; a < 3; ++a) out->momentum[a] = v[2 + a];
+  out->kinetic = v[5];
+  out->umax = v[6];
+  const double wl = v[0], wg = v[13];
+  for (int a = 0; a < 3; ++a) {
+    out->centroid_l[a] = wl != 0 ? v[7 + a] / wl : 0.0;
+    out->velocity_l[a] = wl != 0 ? v[10 + a] / wl : 0.0;
+    out->centroid_g[a] = wg != 0 ? v[14 + a] / wg : 0.0;
+    out->velocity_g[a] = wg != 0 ? v[17 + a] / wg : 0.0;
+  }
+  out->n_l = v[21];
+  out->n_g = v[23];
+  out->p_l = v[21] > 0 ? v[20] / v[21] : 0.0;
+  out->p_g = v[23] > 0 ? v[22] / v[23] : 0.0;
+  out->nonfinite = v[24] != 0.0 || !std::isfinite(v[0]) ? 1 : 0;
+  return out->nonfinite != 0;
 }
 
 // Smallest z-chunk whose tile list fits in `slots` resident workgroups, so that
@@ -368,6 +404,8 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
       if (s != LBM_OK) return s;
       if ((boxes[i].flags ^ boxes[0].flags) & LBM_GRADIENT_CLOSURE)
         return fail(nullptr, LBM_ERR_UNSUPPORTED, "lbm_create: box %d: all boxes of a context must share one closure", i);
+      if ((boxes[i].flags ^ boxes[0].flags) & LBM_HIGH_ORDER_AC)
+        return fail(nullptr, LBM_ERR_UNSUPPORTED, "lbm_create: box %d: all boxes of a context must share LBM_HIGH_ORDER_AC", i);
     }
     if (dev && ((dev->alloc == nullptr) != (dev->free == nullptr)))
       return fail(nullptr, LBM_ERR_ARG, "lbm_create: alloc and free callbacks must be given together");
@@ -376,6 +414,7 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
     if (dev) c->dev = *dev;
     c->precision = boxes[0].precision;
     c->gc = (boxes[0].flags & LBM_GRADIENT_CLOSURE) != 0;
+    c->ho = (boxes[0].flags & LBM_HIGH_ORDER_AC) != 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) {
       delete c;
@@ -410,9 +449,22 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
         b.desc.phi[s] = b.mem[s];
         b.desc.mom[s] = static_cast<char*>(b.mem[s]) + pb;
       }
+      if (c->ho) {
+        b.aux = dev_alloc(c, align256(static_cast<size_t>(b.n) * 6 * sizeof(double)));
+        if (!b.aux) {
+          lbm_destroy(c);
+          return fail(nullptr, LBM_ERR_OOM, "lbm_create: high-order phase buffer allocation failed (box %d)", i);
+        }
+        b.desc.aux = static_cast<double*>(b.aux);
+      }
     }
     c->d_boxes = static_cast<BoxDesc*>(dev_alloc(c, align256(n_boxes * sizeof(BoxDesc))));
-    c->d_diag = static_cast<double*>(dev_alloc(c, align256((lbm::kDiagBlocks + 1) * lbm::kDiagValues * sizeof(double))));
+    int64_t max_n = 1;
+    for (auto& b : c->boxes) max_n = std::max(max_n, b.n);
+    c->diag_bpb = lbm::diag_blocks_per_box(max_n);
+    c->ho_bpb = lbm::high_order_blocks_per_box(max_n);
+    c->d_diag = static_cast<double*>(dev_alloc(
+        c, align256(static_cast<size_t>(n_boxes) * (c->diag_bpb + 1) * lbm::kDiagValues * sizeof(double))));
     if (!c->d_boxes || !c->d_diag) {
       lbm_destroy(c);
       return fail(nullptr, LBM_ERR_OOM, "lbm_create: descriptor allocation failed");
@@ -538,9 +590,13 @@ lbm_status lbm_step_unbatched(lbm_ctx* c, int32_t nsteps) {
   for (size_t i = 0; i < c->boxes.size(); ++i)
     if (!c->boxes[i].initialized) return fail(c, LBM_ERR_STATE, "lbm_step_unbatched: box %zu not initialised", i);
   for (int s = 0; s < nsteps; ++s) {
-    for (auto& bi : c->box_items) {
+    for (size_t k = 0; k < c->box_items.size(); ++k) {
+      const auto& bi = c->box_items[k];
       HIP_TRY(c, lbm::launch_fused(c->precision, c->gc, c->tuning.block_x, c->tuning.block_y, c->d_boxes,
                                    c->d_items + bi.first, bi.second, bi.second, c->parity, c->stream));
+      if (c->ho)
+        HIP_TRY(c, lbm::launch_high_order_phase(c->precision, c->d_boxes, static_cast<int>(k), 1, c->parity,
+                                                c->ho_bpb, c->stream));
     }
     c->parity ^= 1;
   }
@@ -572,30 +628,32 @@ lbm_status lbm_diagnostics(lbm_ctx* c, int32_t box, lbm_diag* out) {
   if (!out) return fail(c, LBM_ERR_ARG, "lbm_diagnostics: out is NULL");
   Box& b = c->boxes[box];
   if (!b.initialized) return fail(c, LBM_ERR_STATE, "lbm_diagnostics: box %d not initialised", box);
-  double* d_out = c->d_diag + lbm::kDiagBlocks * lbm::kDiagValues;
-  HIP_TRY(c, lbm::launch_diagnostics(c->precision, b.desc, c->parity, c->d_diag, d_out, c->stream));
+  double* d_out = c->d_diag + static_cast<size_t>(c->boxes.size()) * c->diag_bpb * lbm::kDiagValues;
+  HIP_TRY(c, lbm::launch_diagnostics(c->precision, c->d_boxes, box, 1, c->parity, c->diag_bpb, c->d_diag, d_out,
+                                     c->stream));
   double v[lbm::kDiagValues];
   HIP_TRY(c, hipMemcpyAsync(v, d_out, sizeof(v), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::memset(out, 0, sizeof(*out));
-  out->phase_mass = v[0];
-  out->pstar_sum = v[1];
-  for (int a = 0; a < 3; ++a) out->momentum[a] = v[2 + a];
-  out->kinetic = v[5];
-  out->umax = v[6];
-  const double wl = v[0], wg = v[13];
-  for (int a = 0; a < 3; ++a) {
-    out->centroid_l[a] = wl != 0 ? v[7 + a] / wl : 0.0;
-    out->velocity_l[a] = wl != 0 ? v[10 + a] / wl : 0.0;
-    out->centroid_g[a] = wg != 0 ? v[14 + a] / wg : 0.0;
-    out->velocity_g[a] = wg != 0 ? v[17 + a] / wg : 0.0;
-  }
-  out->n_l = v[21];
-  out->n_g = v[23];
-  out->p_l = v[21] > 0 ? v[20] / v[21] : 0.0;
-  out->p_g = v[23] > 0 ? v[22] / v[23] : 0.0;
-  out->nonfinite = v[24] != 0.0 || !std::isfinite(v[0]) ? 1 : 0;
-  if (out->nonfinite) return fail(c, LBM_ERR_UNSTABLE, "lbm_diagnostics: non-finite state in box %d", box);
+  if (fill_diag(v, out)) return fail(c, LBM_ERR_UNSTABLE, "lbm_diagnostics: non-finite state in box %d", box);
+  return LBM_OK;
+}
+
+lbm_status lbm_diagnostics_all(lbm_ctx* c, lbm_diag* out) {
+  if (!c) return fail(nullptr, LBM_ERR_ARG, "NULL context");
+  if (!out) return fail(c, LBM_ERR_ARG, "lbm_diagnostics_all: out is NULL");
+  const int nb = static_cast<int>(c->boxes.size());
+  for (int i = 0; i < nb; ++i)
+    if (!c->boxes[i].initialized) return fail(c, LBM_ERR_STATE, "lbm_diagnostics_all: box %d not initialised", i);
+  double* d_out = c->d_diag + static_cast<size_t>(nb) * c->diag_bpb * lbm::kDiagValues;
+  HIP_TRY(c, lbm::launch_diagnostics(c->precision, c->d_boxes, 0, nb, c->parity, c->diag_bpb, c->d_diag, d_out,
+                                     c->stream));
+  std::vector<double> v(static_cast<size_t>(nb) * lbm::kDiagValues);
+  HIP_TRY(c, hipMemcpyAsync(v.data(), d_out, v.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int bad = -1;
+  for (int i = 0; i < nb; ++i)
+    if (fill_diag(v.data() + static_cast<size_t>(i) * lbm::kDiagValues, out + i) && bad < 0) bad = i;
+  if (bad >= 0) return fail(c, LBM_ERR_UNSTABLE, "lbm_diagnostics_all: non-finite state in box %d", bad);
   return LBM_OK;
 }
 
@@ -782,8 +840,10 @@ void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   drop_graphs(c);
-  for (auto& b : c->boxes)
+  for (auto& b : c->boxes) {
     for (int s = 0; s < 2; ++s) dev_free(c, b.mem[s]);
+    dev_free(c, b.aux);
+  }
   dev_free(c, c->d_boxes);
   dev_free(c, c->d_items);
   dev_free(c, c->d_stage);

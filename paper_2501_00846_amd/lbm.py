@@ -26,6 +26,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16_os": 2, "bf16_os": 3}
 PERIODIC, WALL = 0, 1
 LITERAL_ADVECTION = 1
 GRADIENT_CLOSURE = 2
+HIGH_ORDER_AC = 4
 FIELDS = ("phi", "P", "Jx", "Jy", "Jz", "Qxx", "Qyy", "Qzz", "Qxy", "Qxz", "Qyz")
 
 
@@ -82,6 +83,7 @@ _SIGS = {
     "lbm_get_fields": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(lbm_diag)]),
+    "lbm_diagnostics_all": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(lbm_diag)]),
     "lbm_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "lbm_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "lbm_get_state_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
@@ -147,7 +149,8 @@ def make_params(prob, precision="fp64"):
         p.gravity[a] = float(prob.gravity[a])
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.flags = (LITERAL_ADVECTION if getattr(prob, "literal_advection", False) else 0) | \
-        (GRADIENT_CLOSURE if getattr(prob, "gradient_closure", False) else 0)
+        (GRADIENT_CLOSURE if getattr(prob, "gradient_closure", False) else 0) | \
+        (HIGH_ORDER_AC if getattr(prob, "high_order_ac", False) else 0)
     p.rho_l, p.rho_g = float(prob.rho_l), float(prob.rho_g)
     p.nu_l, p.nu_g = float(prob.nu_l), float(prob.nu_g)
     p.sigma, p.mobility, p.width = float(prob.sigma), float(prob.mobility), float(prob.width)
@@ -196,6 +199,19 @@ def lbm_diagnostics(ctx, box):
     st = load_library().lbm_diagnostics(ctx, box, ctypes.byref(d))
     out = {name: (list(getattr(d, name)) if isinstance(getattr(d, name), ctypes.Array)
                   else getattr(d, name)) for name, _ in lbm_diag._fields_}
+    _check(st, ctx)
+    return out
+
+
+def _diag_dict(d):
+    return {name: (list(getattr(d, name)) if isinstance(getattr(d, name), ctypes.Array)
+                   else getattr(d, name)) for name, _ in lbm_diag._fields_}
+
+
+def lbm_diagnostics_all(ctx, n_boxes):
+    arr = (lbm_diag * n_boxes)()
+    st = load_library().lbm_diagnostics_all(ctx, arr)
+    out = [_diag_dict(d) for d in arr]
     _check(st, ctx)
     return out
 
@@ -367,6 +383,9 @@ class Context:
 
     def diagnostics(self, box):
         return lbm_diagnostics(self.ctx, box)
+
+    def diagnostics_all(self):
+        return lbm_diagnostics_all(self.ctx, len(self.problems))
 
     # stepping ----------------------------------------------------------------
     def step(self, n=1):

@@ -164,3 +164,16 @@ def test_noalloc_step_rejects_tile_lists_beyond_its_static_scratch():
     st, msg = _noalloc(big, tuning=lbm.lbm_tuning(34, 15, 10, 0))
     assert st == -1 and "scratch" in msg and "33280" in msg
     assert _noalloc(big)[0] == 0  # the default z-chunk fits
+
+
+def test_high_order_variant_needs_four_nodes_on_wall_axes():
+    p = _params(nz=3, flags=4)
+    p.bc[2] = WALL
+    st, _, msg = _create([p])
+    assert st == -1 and ">= 4" in msg
+    p2 = _params(nz=3, flags=4)  # periodic axes take any size
+    p3 = _params(flags=4)
+    p3.bc[0] = WALL
+    st, _, msg = _create([p2, _params()])
+    assert st == -2 and "LBM_HIGH_ORDER_AC" in msg
+    assert _noalloc(p3)[0] == -2

@@ -162,6 +162,32 @@ def test_observables_and_diagnostics_match_oracle():
     assert d["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_diagnostics_of_all_boxes_in_one_launch(precision):
+    """lbm_diagnostics_all reduces every box of an ensemble in one launch and
+    gives, box by box, bitwise what lbm_diagnostics gives; each box agrees with
+    the oracle's diagnostics of its own (decoded) state."""
+    dims = [(24, 20, 9), (37, 29, 23), (8, 8, 8), (61, 13, 17)]
+    bcs = [(P_, P_, P_), (P_, W_, W_), (W_, P_, P_), (W_, W_, W_)]
+    probs = [_prob(d, b) for d, b in zip(dims, bcs)]
+    with lbm.Context(probs, precision) as ctx:
+        for i, p in enumerate(probs):
+            ctx.set_state(i, smooth_random_state(p, 40 + i).reshape(-1))
+        ctx.step(3)
+        together = ctx.diagnostics_all()
+        alone = [ctx.diagnostics(i) for i in range(len(probs))]
+        states = [ctx.get_state(i) for i in range(len(probs))]
+    assert len(together) == len(probs)
+    for i, (t, a) in enumerate(zip(together, alone)):
+        assert t == a, i
+        dg = S.diagnostics(array_state(states[i]), probs[i])
+        abs_p = 1e-13 * np.abs(states[i][1]).sum()
+        for key in ("phase_mass", "pstar_sum", "kinetic", "umax", "p_l", "p_g", "n_l", "n_g"):
+            assert t[key] == pytest.approx(dg[key], rel=1e-10, abs=abs_p + 1e-30), (i, key)
+        for key in ("momentum", "centroid_l", "velocity_l", "centroid_g", "velocity_g"):
+            assert np.allclose(t[key], dg[key], rtol=1e-9, atol=1e-16), (i, key)
+
+
 def test_nonfinite_state_is_reported():
     prob = _prob((8, 8, 8), (P_, P_, P_))
     state = smooth_random_state(prob, 1)
@@ -170,6 +196,9 @@ def test_nonfinite_state_is_reported():
         ctx.set_state(0, state.reshape(-1))
         with pytest.raises(lbm.LbmError) as ei:
             ctx.diagnostics(0)
+        assert ei.value.status == -5
+        with pytest.raises(lbm.LbmError) as ei:
+            ctx.diagnostics_all()
         assert ei.value.status == -5
         with pytest.raises(lbm.LbmError):
             ctx.fields(0)
