@@ -125,6 +125,18 @@ __device__ __forceinline__ int map_axis(int i, int n, int wall) {
 // hardware square root and reciprocal (about 1 ulp), which the FP32 modes'
 // error budget absorbs.
 __device__ __forceinline__ double inv_norm_eps(double s) { return 1.0 / (sqrt(s) + 1e-12); }
+
+// 1 / d for d > 0 (finite, normal): the hardware reciprocal estimate refined by
+// two Newton steps r <- r + r (1 - d r), each squaring the relative error, so
+// the result is within a rounding or two of the correctly rounded quotient --
+// 5 instructions instead of the ~11 of the IEEE division sequence.
+__device__ __forceinline__ double rcp_newton(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
 __device__ __forceinline__ float inv_norm_eps(float s) {
   return __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(s) + 1e-12f);
 }
@@ -200,26 +212,28 @@ template <class R> struct Acc {
   __device__ void zero() { p = jx = jy = jz = xx = yy = zz = xy = xz = yz = R(0); }
 };
 
-// Add the moments of 9 populations v[(cy+1)*3 + (cx+1)] sharing c_z = cz.
+// Add the moments of 9 populations sharing c_z = cz, each weighted by its
+// lattice weight: v[(cy+1)*3 + (cx+1)] holds g(c)/216 and the population is
+// w1(cx) w1(cy) w1(cz) v with w1 = (1, 4, 1) (216 w(c)).
 // FRESH: the accumulator holds nothing yet, so the sums are assigned (adding
 // them to zero would cost an instruction each: x + 0 is not x for x = -0).
 template <class R, int CZ, bool FRESH = false>
 __device__ __forceinline__ void accum_group(const R* v, Acc<R>& a) {
-  // along x for each c_y row: s0 = sum, s1 = sum cx, s2 = sum cx^2
+  // along x for each c_y row: s0 = sum w1 v, s1 = sum cx w1 v, s2 = sum cx^2 w1 v
   R s0[3], s1[3], s2[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     const R l = v[r * 3 + 0], c = v[r * 3 + 1], h = v[r * 3 + 2];
     s2[r] = h + l;
     s1[r] = h - l;
-    s0[r] = s2[r] + c;
+    s0[r] = s2[r] + R(4) * c;
   }
   const R m02 = s0[2] + s0[0];
-  const R m00 = m02 + s0[1];
+  const R m00 = m02 + R(4) * s0[1];
   const R m01 = s0[2] - s0[0];
-  const R m10 = s1[0] + s1[1] + s1[2];
+  const R m10 = s1[0] + s1[2] + R(4) * s1[1];
   const R m11 = s1[2] - s1[0];
-  const R m20 = s2[0] + s2[1] + s2[2];
+  const R m20 = s2[0] + s2[2] + R(4) * s2[1];
   if constexpr (FRESH) {
     static_assert(CZ > 0, "only the group entering a new output plane starts it");
     a.p = m00;
@@ -234,13 +248,22 @@ __device__ __forceinline__ void accum_group(const R* v, Acc<R>& a) {
     a.yz = m01;
     return;
   }
+  if (CZ == 0) {
+    a.p += R(4) * m00;
+    a.jx += R(4) * m10;
+    a.jy += R(4) * m01;
+    a.xx += R(4) * m20;
+    a.yy += R(4) * m02;
+    a.xy += R(4) * m11;
+    return;
+  }
   a.p += m00;
   a.jx += m10;
   a.jy += m01;
   a.xx += m20;
   a.yy += m02;
   a.xy += m11;
-  if (CZ != 0) {
+  {
     a.zz += m00;
     if (CZ > 0) { a.jz += m00; a.xz += m10; a.yz += m01; }
     else        { a.jz -= m00; a.xz -= m10; a.yz -= m01; }
@@ -370,6 +393,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     const R kappa_ac = static_cast<R>(b.kappa_ac);
     const R mob = static_cast<R>(b.mobility);
     const R drho3 = static_cast<R>(b.drho * (1.0 / 3.0));
+    const R grx = static_cast<R>(b.grav[0]), gry = static_cast<R>(b.grav[1]), grz = static_cast<R>(b.grav[2]);
     const bool literal = (b.flags & 1) != 0;
 
     const int z0 = item.z0, z1 = item.z1;
@@ -630,7 +654,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const double rho = b.rho_g + phid * b.drho;
       const double nu = b.nu_g + phid * b.dnu;
       const double tau = 3.0 * nu + 0.5;        // 1 / omega
-      const double r_rt = 1.0 / (rho * tau);    // one division for 1/rho and omega
+      const double r_rt = rcp_newton(rho * tau);  // one reciprocal for 1/rho and omega
       const double inv_rho = tau * r_rt;
       const double om_d = rho * r_rt;
       const double bfac = 1.0 - b.rho_ref * inv_rho;  // body acceleration factor
@@ -683,9 +707,10 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R qgx = Txx * gmx + Txy * gmy + Txz * gz;
       const R qgy = Txy * gmx + Tyy * gmy + Tyz * gz;
       const R qgz = Txz * gmx + Tyz * gmy + Tzz * gz;
-      const R ax = csp * gmx + cvis * qgx + static_cast<R>(b.grav[0] * bfac);
-      const R ay = csp * gmy + cvis * qgy + static_cast<R>(b.grav[1] * bfac);
-      const R az = csp * gz + cvis * qgz + static_cast<R>(b.grav[2] * bfac);
+      const R bf = static_cast<R>(bfac);
+      const R ax = csp * gmx + cvis * qgx + grx * bf;
+      const R ay = csp * gmy + cvis * qgy + gry * bf;
+      const R az = csp * gz + cvis * qgz + grz * bf;
       const R ux = Jx + R(0.5) * ax;
       const R uy = Jy + R(0.5) * ay;
       const R uz = Jz + R(0.5) * az;
@@ -699,41 +724,43 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R Axz = GC ? Txz : Txz + R(0.25) * ax * az;
       const R Ayz = GC ? Tyz : Tyz + R(0.25) * ay * az;
 
-      // monomial coefficients of g(c) = f_post(c) / w(c), pre-scaled by 1/216
-      const R usq = ux * ux + uy * uy + uz * uz;
-      const R trA = Axx + Ayy + Azz;
-      const R ua = ux * ax + uy * ay + uz * az;
-      const R Aux = Axx * ux + Axy * uy + Axz * uz;
-      const R Auy = Axy * ux + Ayy * uy + Ayz * uz;
-      const R Auz = Axz * ux + Ayz * uy + Azz * uz;
+      // monomial coefficients of g(c) = f_post(c) / w(c), pre-scaled by 1/216,
+      // written with B = (1 - omega) a2 and S_aa = u_a^2 + B_aa.  The relaxed
+      // part of the first-order coefficients combines as
+      // 13.5 u_x A_xx - 4.5 u_x tr(A) - 9 (A u)_x = -4.5 u_x (A_yy + A_zz)
+      // - 9 (A_xy u_y + A_xz u_z), and likewise for y and z.
+      const R Bxx = om1 * Axx, Byy = om1 * Ayy, Bzz = om1 * Azz;
+      const R Bxy = om1 * Axy, Bxz = om1 * Axz, Byz = om1 * Ayz;
+      const R Sxx = ux * ux + Bxx, Syy = uy * uy + Byy, Szz = uz * uz + Bzz;
+      const R Exx = Sxx + ux * ax, Eyy = Syy + uy * ay, Ezz = Szz + uz * az;
       constexpr R s = R(1.0 / 216.0);
-      const R G0 = s * (P - R(1.5) * (usq + om1 * trA + ua));
-      const R Gx = s * (R(3) * ux - R(4.5) * ux * (uy * uy + uz * uz) +
-                        om1 * (R(13.5) * ux * Axx - R(4.5) * ux * trA - R(9) * Aux) + R(1.5) * ax);
-      const R Gy = s * (R(3) * uy - R(4.5) * uy * (ux * ux + uz * uz) +
-                        om1 * (R(13.5) * uy * Ayy - R(4.5) * uy * trA - R(9) * Auy) + R(1.5) * ay);
-      const R Gz = s * (R(3) * uz - R(4.5) * uz * (ux * ux + uy * uy) +
-                        om1 * (R(13.5) * uz * Azz - R(4.5) * uz * trA - R(9) * Auz) + R(1.5) * az);
-      const R Gxx = (R(4.5) * s) * (ux * ux + om1 * Axx + ux * ax);
-      const R Gyy = (R(4.5) * s) * (uy * uy + om1 * Ayy + uy * ay);
-      const R Gzz = (R(4.5) * s) * (uz * uz + om1 * Azz + uz * az);
-      const R Gxy = s * (R(9) * (ux * uy + om1 * Axy) + R(4.5) * (ux * ay + uy * ax));
-      const R Gxz = s * (R(9) * (ux * uz + om1 * Axz) + R(4.5) * (ux * az + uz * ax));
-      const R Gyz = s * (R(9) * (uy * uz + om1 * Ayz) + R(4.5) * (uy * az + uz * ay));
+      const R G0 = s * P - (R(1.5) * s) * (Exx + Eyy + Ezz);
+      const R Gx = s * (R(3) * ux + R(1.5) * ax) - (R(4.5) * s) * (ux * (Syy + Szz) + R(2) * (Bxy * uy + Bxz * uz));
+      const R Gy = s * (R(3) * uy + R(1.5) * ay) - (R(4.5) * s) * (uy * (Sxx + Szz) + R(2) * (Bxy * ux + Byz * uz));
+      const R Gz = s * (R(3) * uz + R(1.5) * az) - (R(4.5) * s) * (uz * (Sxx + Syy) + R(2) * (Bxz * ux + Byz * uy));
+      const R Gxx = (R(4.5) * s) * Exx;
+      const R Gyy = (R(4.5) * s) * Eyy;
+      const R Gzz = (R(4.5) * s) * Ezz;
+      const R hx = R(0.5) * ax, hy = R(0.5) * ay, hz = R(0.5) * az;
+      const R Gxy = (R(9) * s) * (ux * (uy + hy) + (uy * hx + Bxy));
+      const R Gxz = (R(9) * s) * (ux * (uz + hz) + (uz * hx + Bxz));
+      const R Gyz = (R(9) * s) * (uy * (uz + hz) + (uz * hy + Byz));
       constexpr R s3 = R(13.5 / 216.0);
-      const R Gxxy = s3 * (ux * ux * uy + om1 * (uy * Axx + R(2) * ux * Axy));
-      const R Gxxz = s3 * (ux * ux * uz + om1 * (uz * Axx + R(2) * ux * Axz));
-      const R Gyyx = s3 * (uy * uy * ux + om1 * (ux * Ayy + R(2) * uy * Axy));
-      const R Gyyz = s3 * (uy * uy * uz + om1 * (uz * Ayy + R(2) * uy * Ayz));
-      const R Gzzx = s3 * (uz * uz * ux + om1 * (ux * Azz + R(2) * uz * Axz));
-      const R Gzzy = s3 * (uz * uz * uy + om1 * (uy * Azz + R(2) * uz * Ayz));
-      const R Gxyz = R(27.0 / 216.0) * (ux * uy * uz + om1 * (ux * Ayz + uy * Axz + uz * Axy));
+      const R Gxxy = s3 * (uy * Sxx + R(2) * (ux * Bxy));
+      const R Gxxz = s3 * (uz * Sxx + R(2) * (ux * Bxz));
+      const R Gyyx = s3 * (ux * Syy + R(2) * (uy * Bxy));
+      const R Gyyz = s3 * (uz * Syy + R(2) * (uy * Byz));
+      const R Gzzx = s3 * (ux * Szz + R(2) * (uz * Bxz));
+      const R Gzzy = s3 * (uy * Szz + R(2) * (uz * Byz));
+      const R Gxyz = R(27.0 / 216.0) * (ux * (uy * uz + Byz) + (uy * Bxz + uz * Bxy));
 
-      // evaluate w(c) g(c) at the 27 velocities: x, then y, then z, with the
-      // one-dimensional weights (1, 4, 1) (x 1/216 folded in above)
-      auto xb = [](R c0, R c1, R c2, R* o) { o[0] = c0 - c1 + c2; o[1] = R(4) * c0; o[2] = c0 + c1 + c2; };
-      auto xb2 = [](R c0, R c1, R* o) { o[0] = c0 - c1; o[1] = R(4) * c0; o[2] = c0 + c1; };
-      auto xb1 = [](R c0, R* o) { o[0] = c0; o[1] = R(4) * c0; o[2] = c0; };
+      // evaluate g(c) / 216 at the 27 velocities: x, then y, then z.  The
+      // lattice weights w(c) = (1, 4, 1) x (1, 4, 1) x (1, 4, 1) / 216 are
+      // applied where the pulled populations are summed (accum_group), as
+      // multiply-adds that replace plain adds there.
+      auto xb = [](R c0, R c1, R c2, R* o) { o[0] = c0 - c1 + c2; o[1] = c0; o[2] = c0 + c1 + c2; };
+      auto xb2 = [](R c0, R c1, R* o) { o[0] = c0 - c1; o[1] = c0; o[2] = c0 + c1; };
+      auto xb1 = [](R c0, R* o) { o[0] = c0; o[1] = c0; o[2] = c0; };
       R B00[3], B01[3], B02[3], B10[3], B11[3], B12[3], B20[3], B21[3];
       xb(G0, Gx, Gxx, B00);
       xb(Gy, Gxy, Gxxy, B01);
@@ -751,16 +778,16 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
           const int cy = cyi - 1, cx = cxi - 1;
           R p0, p1, p2;
           if (cy == 0) {
-            p0 = R(4) * B00[cxi];
-            p1 = R(4) * B10[cxi];
-            p2 = R(4) * B20[cxi];
+            p0 = B00[cxi];
+            p1 = B10[cxi];
+            p2 = B20[cxi];
           } else {
             p0 = B00[cxi] + B02[cxi] + (cy > 0 ? B01[cxi] : -B01[cxi]);
             p1 = B10[cxi] + B12[cxi] + (cy > 0 ? B11[cxi] : -B11[cxi]);
             p2 = B20[cxi] + (cy > 0 ? B21[cxi] : -B21[cxi]);
           }
           const R fm = p0 + p2 - p1;  // cz = -1
-          const R f0 = R(4) * p0;     // cz = 0
+          const R f0 = p0;            // cz = 0
           const R fp = p0 + p2 + p1;  // cz = +1
           if (cx == 0 && cy == 0) {
             fo[0] = fm;
