@@ -1015,12 +1015,22 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
   const int nx = b.nx, ny = b.ny, nz = b.nz;
   const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
   const gptr<const TM> fmom = (gptr<const TM>)b.mom[parity];
+  // loads without a per-moment runtime test (see diag_partial_kernel): the
+  // closure's moment count selects one of two unrolled blocks
   double m[10];
   finite = true;
-  for (int k = 0; k < 10; ++k) {
-    m[k] = k < b.nmom ? dec<double>(fmom[mom_at(b, k, x, y, z)], b.enc_off[k], b.enc_inv[k]) : 0.0;
-    finite = finite && isfinite(m[k]);
-  }
+  auto load_moments = [&](auto nm) {
+    constexpr int NMOM = decltype(nm)::value;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) m[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k) {
+      m[k] = dec<double>(fmom[mom_at(b, k, x, y, z)], b.enc_off[k], b.enc_inv[k]);
+      finite = finite && isfinite(m[k]);
+    }
+  };
+  if (b.nmom == 4) load_moments(std::integral_constant<int, 4>{});
+  else load_moments(std::integral_constant<int, 10>{});
   phi = dec<double>(fphi[phi_at(b, x, y, z)], 0.f, 1.f);
   finite = finite && isfinite(phi);
   // neighbour coordinates per axis (wrap or mirror) and wall-crossing flags,
@@ -1129,42 +1139,182 @@ __device__ __forceinline__ double wave_combine(int k, double v) {
   return v;
 }
 
+// x-y parts of the isotropic 27-point stencils on one plane of a field, at
+// column (x, y) with neighbour columns xs[cx + 1], ys[cy + 1] (wrap / mirror
+// already resolved): F[0] = s_x s_y f, F[1] = s_y d_x f, F[2] = s_x d_y f with
+// s = (1, 4, 1) and d = (-1, 0, 1), F[3] = f at the column.  ld(xm, ym, cx, cy)
+// returns the decoded value of the (mapped) neighbour column.
+template <class Load>
+__device__ __forceinline__ void diag_filter(const Load& ld, const int xs[3], const int ys[3], double F[4]) {
+  double sx[3], dx[3];
+  for (int cy = 0; cy < 3; ++cy) {
+    const double l = ld(xs[0], ys[cy], 0, cy), c = ld(xs[1], ys[cy], 1, cy), h = ld(xs[2], ys[cy], 2, cy);
+    sx[cy] = l + 4.0 * c + h;
+    dx[cy] = h - l;
+    if (cy == 1) F[3] = c;
+  }
+  F[0] = sx[0] + 4.0 * sx[1] + sx[2];
+  F[1] = dx[0] + 4.0 * dx[1] + dx[2];
+  F[2] = sx[2] - sx[0];
+}
+
+constexpr int kDiagZ = 64;  // planes per work unit of the diagnostics z-march
+
 // One launch covers boxes box0 .. box0 + gridDim.y - 1 of the descriptor
-// array; gridDim.x workgroups share each box (grid-stride over its nodes) and
-// write one partial per value: partials[(blockIdx.y * gridDim.x + blockIdx.x)
-// * kDiagValues + k].
-template <class PR>
+// array; gridDim.x workgroups share each box and write one partial per value:
+// partials[(blockIdx.y * gridDim.x + blockIdx.x) * kDiagValues + k].
+// A work unit is one column (x, y) over up to kDiagZ planes; consecutive
+// threads take consecutive x, so every load is coalesced.  Each thread keeps
+// the x-y filtered phi planes z-1, z, z+1 in registers (and, for the gradient
+// closure, those of J), so a node costs 9 loads and conversions of phi
+// instead of the 27 of a direct stencil; the node quantities are those of
+// node_obs in FP64: rho, u = J + a/2 with the full force, p = rho cs^2 p*.
+template <class PR, bool GC>
 __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity,
                                                                     double* __restrict__ partials) {
+  using TM = typename PR::TM;
+  using TP = typename PR::TP;
   __shared__ double red[kDiagWaves][kDiagValues];
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   double acc[kDiagValues];
   for (int k = 0; k < kDiagValues; ++k) acc[k] = 0.0;
-  const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    int x, y, z;
-    node_xyz(b, i, x, y, z);
-    double rho, u[3], phi, p, ps;
-    bool fin;
-    node_obs<PR>(b, parity, x, y, z, rho, u, phi, p, ps, fin);
-    const double sp = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const double pos[3] = {double(x), double(y), double(z)};
-    acc[0] += phi;
-    acc[1] += ps;
-    for (int a = 0; a < 3; ++a) acc[2 + a] += rho * u[a];
-    acc[5] += 0.5 * rho * sp;
-    acc[6] = fmax(acc[6], sqrt(sp));
-    for (int a = 0; a < 3; ++a) {
-      acc[7 + a] += phi * pos[a];
-      acc[10 + a] += phi * u[a];
-      acc[14 + a] += (1.0 - phi) * pos[a];
-      acc[17 + a] += (1.0 - phi) * u[a];
+  const int nx = b.nx, ny = b.ny, nz = b.nz;
+  const int64_t ncol = static_cast<int64_t>(nx) * ny;
+  const int64_t units = ncol * ((nz + kDiagZ - 1) / kDiagZ);
+  const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
+  const gptr<const TM> fmom = (gptr<const TM>)b.mom[parity];
+  for (int64_t un = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; un < units;
+       un += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t col = un % ncol;
+    const int x = static_cast<int>(col % nx), y = static_cast<int>(col / nx);
+    const int z0 = static_cast<int>(un / ncol) * kDiagZ, z1 = min(z0 + kDiagZ, nz);
+    int xs[3], ys[3], kx[3], ky[3];
+    for (int c = -1; c <= 1; ++c) {
+      xs[c + 1] = map_axis(x + c, nx, b.wall[0], kx[c + 1]);
+      ys[c + 1] = map_axis(y + c, ny, b.wall[1], ky[c + 1]);
     }
-    acc[13] += 1.0 - phi;
-    if (phi >= 0.98) { acc[20] += p; acc[21] += 1.0; }
-    if (phi <= 0.02) { acc[22] += p; acc[23] += 1.0; }
-    if (!fin) acc[24] = 1.0;
+    // Raw (still encoded) phi of the 3 x 3 columns of the next plane and the
+    // node's moments are loaded one plane ahead, so their memory latency
+    // overlaps the node's arithmetic.  The moment count is a compile-time
+    // constant: a per-moment runtime test would put each load in a basic
+    // block of its own, and with 16- or 32-bit storage the conversion after
+    // it would wait for that load before the next one is issued.
+    constexpr int NMOM = GC ? 4 : 10;
+    TP rph[9];
+    TM rm[NMOM];
+    auto issue_phi = [&](int q) {
+      const int zq = map_axis(q, nz, b.wall[2]);
+#pragma unroll
+      for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx) rph[cy * 3 + cx] = fphi[phi_at(b, xs[cx], ys[cy], zq)];
+    };
+    auto issue_mom = [&](int zm) {
+#pragma unroll
+      for (int k = 0; k < NMOM; ++k) rm[k] = fmom[mom_at(b, k, x, y, zm)];
+    };
+    auto filter_phi = [&](double F[4]) {
+      auto ld = [&](int, int, int cx, int cy) { return dec<double>(rph[cy * 3 + cx], 0.f, 1.f); };
+      diag_filter(ld, xs, ys, F);
+    };
+    // gradient closure: filtered J of plane q (J ghosts: minus the mirrored
+    // value per crossed wall)
+    auto filter_J = [&](int q, double JF[3][4]) {
+      int kz;
+      const int zq = map_axis(q, nz, b.wall[2], kz);
+      for (int a = 0; a < 3; ++a) {
+        auto ldj = [&](int xm, int ym, int cx, int cy) {
+          const double v = dec<double>(fmom[mom_at(b, 1 + a, xm, ym, zq)], b.enc_off[1 + a], b.enc_inv[1 + a]);
+          return ((kx[cx] + ky[cy] + kz) & 1) ? -v : v;
+        };
+        diag_filter(ldj, xs, ys, JF[a]);
+      }
+    };
+    double Fm[4], F0[4], Fn[4];
+    double JFm[GC ? 3 : 1][4], JF0[GC ? 3 : 1][4], JFn[GC ? 3 : 1][4];
+    issue_phi(z0 - 1);
+    filter_phi(Fm);
+    issue_phi(z0);
+    filter_phi(F0);
+    if constexpr (GC) {
+      filter_J(z0 - 1, JFm);
+      filter_J(z0, JF0);
+    }
+    issue_phi(z0 + 1);
+    issue_mom(z0);
+    for (int z = z0; z < z1; ++z) {
+      filter_phi(Fn);  // plane z + 1
+      if constexpr (GC) filter_J(z + 1, JFn);
+      double m[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < NMOM; ++k) m[k] = dec<double>(rm[k], b.enc_off[k], b.enc_inv[k]);
+      if (z + 1 < z1) {
+        issue_phi(z + 2);
+        issue_mom(z + 1);
+      }
+      const double phi = F0[3];
+      const double g[3] = {(Fm[1] + 4.0 * F0[1] + Fn[1]) * (1.0 / 72.0), (Fm[2] + 4.0 * F0[2] + Fn[2]) * (1.0 / 72.0),
+                           (Fn[0] - Fm[0]) * (1.0 / 72.0)};
+      const double lap = (Fm[0] + 4.0 * F0[0] + Fn[0]) * (1.0 / 36.0) - 6.0 * phi;
+      bool fin = isfinite(phi);
+#pragma unroll
+      for (int k = 0; k < NMOM; ++k) fin = fin && isfinite(m[k]);
+      const double phic = fmin(fmax(phi, 0.0), 1.0);
+      const double rho = b.rho_g + phic * b.drho;
+      const double nu = b.nu_g + phic * b.dnu;
+      const double om = 1.0 / (3.0 * nu + 0.5);
+      const double mu = b.beta4 * phi * (phi - 1.0) * (phi - 0.5) - b.kappa_mu * lap;
+      const double P = m[0];
+      double Q[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+      if constexpr (GC) {
+        double gJ[3][3];  // gJ[a][c] = d_c J_a
+        for (int a = 0; a < 3; ++a) {
+          gJ[a][0] = (JFm[a][1] + 4.0 * JF0[a][1] + JFn[a][1]) * (1.0 / 72.0);
+          gJ[a][1] = (JFm[a][2] + 4.0 * JF0[a][2] + JFn[a][2]) * (1.0 / 72.0);
+          gJ[a][2] = (JFn[a][0] - JFm[a][0]) * (1.0 / 72.0);
+        }
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) Q[a][c] = -(1.0 / 3.0) / om * (gJ[a][c] + gJ[c][a]);
+      }
+      double u[3];
+      for (int a = 0; a < 3; ++a) {
+        double qg = 0;
+        for (int c = 0; c < 3; ++c) qg += Q[a][c] * g[c] * b.drho;
+        const double F = mu * g[a] - P * (1.0 / 3.0) * b.drho * g[a] - 3.0 * nu * om * qg +
+                         (rho - b.rho_ref) * b.grav[a];
+        u[a] = m[1 + a] + 0.5 * F / rho;
+      }
+      const double p = rho * (1.0 / 3.0) * P;
+      const double sp = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+      const double pos[3] = {double(x), double(y), double(z)};
+      acc[0] += phi;
+      acc[1] += P;
+      for (int a = 0; a < 3; ++a) acc[2 + a] += rho * u[a];
+      acc[5] += 0.5 * rho * sp;
+      acc[6] = fmax(acc[6], sqrt(sp));
+      for (int a = 0; a < 3; ++a) {
+        acc[7 + a] += phi * pos[a];
+        acc[10 + a] += phi * u[a];
+        acc[14 + a] += (1.0 - phi) * pos[a];
+        acc[17 + a] += (1.0 - phi) * u[a];
+      }
+      acc[13] += 1.0 - phi;
+      if (phi >= 0.98) { acc[20] += p; acc[21] += 1.0; }
+      if (phi <= 0.02) { acc[22] += p; acc[23] += 1.0; }
+      if (!fin) acc[24] = 1.0;
+      for (int k = 0; k < 4; ++k) {
+        Fm[k] = F0[k];
+        F0[k] = Fn[k];
+      }
+      if constexpr (GC)
+        for (int a = 0; a < 3; ++a)
+          for (int k = 0; k < 4; ++k) {
+            JFm[a][k] = JF0[a][k];
+            JF0[a][k] = JFn[a][k];
+          }
+    }
   }
   // wavefront reductions (unrolled: a runtime index into acc would move the
   // accumulators from registers to scratch memory), then the waves of the
@@ -1499,13 +1649,17 @@ int diag_blocks_per_box(int64_t max_nodes) {
   return static_cast<int>(nb < 1 ? 1 : (nb > kDiagBlocks ? kDiagBlocks : nb));
 }
 
-hipError_t launch_diagnostics(int precision, const BoxDesc* d_boxes, int box0, int nbox, int parity,
+hipError_t launch_diagnostics(int precision, bool gc, const BoxDesc* d_boxes, int box0, int nbox, int parity,
                               int blocks_per_box, double* d_partials, double* d_out, hipStream_t stream) {
   if (nbox <= 0 || blocks_per_box <= 0) return hipErrorInvalidValue;
   hipError_t e = dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
-    hipLaunchKernelGGL((diag_partial_kernel<PR>), dim3(blocks_per_box, nbox), dim3(kDiagThreads), 0, stream, d_boxes,
-                       box0, parity, d_partials);
+    if (gc)
+      hipLaunchKernelGGL((diag_partial_kernel<PR, true>), dim3(blocks_per_box, nbox), dim3(kDiagThreads), 0, stream,
+                         d_boxes, box0, parity, d_partials);
+    else
+      hipLaunchKernelGGL((diag_partial_kernel<PR, false>), dim3(blocks_per_box, nbox), dim3(kDiagThreads), 0, stream,
+                         d_boxes, box0, parity, d_partials);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;

@@ -120,7 +120,8 @@ int diag_blocks_per_box(int64_t max_nodes);
 // doubles), then kDiagValues doubles per box into d_out (box after box).  The
 // order of every sum is fixed by blocks_per_box alone, so a box gives bitwise
 // the same values whether it is reduced alone or with the others.
-hipError_t launch_diagnostics(int precision, const BoxDesc* d_boxes, int box0, int nbox, int parity,
+// gc: the boxes use the gradient closure (every box of a launch alike).
+hipError_t launch_diagnostics(int precision, bool gc, const BoxDesc* d_boxes, int box0, int nbox, int parity,
                               int blocks_per_box, double* d_partials, double* d_out, hipStream_t stream);
 
 }  // namespace lbm

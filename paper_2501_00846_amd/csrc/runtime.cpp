@@ -629,7 +629,7 @@ lbm_status lbm_diagnostics(lbm_ctx* c, int32_t box, lbm_diag* out) {
   Box& b = c->boxes[box];
   if (!b.initialized) return fail(c, LBM_ERR_STATE, "lbm_diagnostics: box %d not initialised", box);
   double* d_out = c->d_diag + static_cast<size_t>(c->boxes.size()) * c->diag_bpb * lbm::kDiagValues;
-  HIP_TRY(c, lbm::launch_diagnostics(c->precision, c->d_boxes, box, 1, c->parity, c->diag_bpb, c->d_diag, d_out,
+  HIP_TRY(c, lbm::launch_diagnostics(c->precision, c->gc, c->d_boxes, box, 1, c->parity, c->diag_bpb, c->d_diag, d_out,
                                      c->stream));
   double v[lbm::kDiagValues];
   HIP_TRY(c, hipMemcpyAsync(v, d_out, sizeof(v), hipMemcpyDeviceToHost, c->stream));
@@ -645,7 +645,7 @@ lbm_status lbm_diagnostics_all(lbm_ctx* c, lbm_diag* out) {
   for (int i = 0; i < nb; ++i)
     if (!c->boxes[i].initialized) return fail(c, LBM_ERR_STATE, "lbm_diagnostics_all: box %d not initialised", i);
   double* d_out = c->d_diag + static_cast<size_t>(nb) * c->diag_bpb * lbm::kDiagValues;
-  HIP_TRY(c, lbm::launch_diagnostics(c->precision, c->d_boxes, 0, nb, c->parity, c->diag_bpb, c->d_diag, d_out,
+  HIP_TRY(c, lbm::launch_diagnostics(c->precision, c->gc, c->d_boxes, 0, nb, c->parity, c->diag_bpb, c->d_diag, d_out,
                                      c->stream));
   std::vector<double> v(static_cast<size_t>(nb) * lbm::kDiagValues);
   HIP_TRY(c, hipMemcpyAsync(v.data(), d_out, v.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
