@@ -75,8 +75,11 @@ def make_cases(config):
 
 
 def kernel_hash():
+    """Hash of the sources the fused step is compiled from (its kernel, the
+    device helpers it shares, the state layout it reads), which keys the
+    committed counter summaries."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "lbm_internal.h"):
+    for f in ("fused_step.hip", "device_common.h", "state_layout.h"):
         with open(os.path.join(ROOT, "paper_2501_00846_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -6,8 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "noalloc.hip"),
-           os.path.join(HERE, "csrc", "runtime.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fused_step.hip", "aux_kernels.hip", "noalloc.hip", "runtime.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
