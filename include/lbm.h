@@ -93,8 +93,8 @@ enum {
    * solver keeps the second-order stencils of Sec. II.C).  Wall axes need
    * at least 4 nodes.  Each step then also keeps 6 doubles per node of
    * device memory (velocity and sharpening flux of level n) and runs two
-   * more kernels.  All boxes of a context must agree on this flag; not
-   * available through lbm_step_noalloc. */
+   * more kernels.  All boxes of a context must agree on this flag and, with
+   * it, on LBM_LITERAL_ADVECTION; not available through lbm_step_noalloc. */
   LBM_HIGH_ORDER_AC = 4
 };
 

@@ -452,112 +452,305 @@ __global__ void __launch_bounds__(kDiagThreads) diag_final_kernel(const double* 
 // isotropic and in the ratio 1 : 4, so the combination removes them.  The
 // flow solver keeps the second-order stencils (the fused step is unchanged;
 // its phi output is overwritten).  Two kernels, both reading level n:
-//   ho_flux_kernel  per node: u = J + a/2 with the forces of Sec. II.C
-//                   (node_obs, FP64) and S = phi (1 - phi) n4, n4 the unit
-//                   fourth-order gradient; 6 doubles into b.aux;
+//   ho_flux_kernel  per node: u = J + a/2 with the forces of Sec. II.C (in
+//                   FP64, as the diagnostics compute it) and S = phi (1 - phi)
+//                   n4, n4 the unit fourth-order gradient; 6 doubles into
+//                   b.aux;
 //   ho_phase_kernel per node: phi' = phi - div4(phi u) + M lap4(phi)
 //                   - (4M/W) div4(S), or u . grad4(phi) for the printed
 //                   advection.  Neighbours beyond a wall are mirrored nodes,
 //                   with u negated per crossed wall and the crossed
 //                   components of S negated (the normal of the mirrored phi).
+// Both march along z.  D1 and D2 are each separable: weights (1, 4, 1) and
+// (-1, 0, 1) per axis, at taps +-1 or +-2.  A kernel filters every plane it
+// meets in x and y once, keeps the filtered planes z-2 .. z+2 in registers,
+// and combines them along z.
 
-// phi of node (x, y, z), coordinates already inside the box
-template <class PR>
-__device__ __forceinline__ double phi_node(const BoxDesc& b, int parity, int x, int y, int z) {
-  using TP = typename PR::TP;
-  return dec<double>(((gptr<const TP>)b.phi[parity])[phi_at(b, x, y, z)], 0.f, 1.f);
-}
+constexpr int kHoZ = 64;  // planes per work unit / tile of the z-marches
 
-template <class PR>
+// u and S = phi (1 - phi) n4 per node into b.aux (6 compact planes).  Work
+// units: one column (x, y) over up to kHoZ planes, consecutive threads on
+// consecutive x.  Per plane the thread filters phi over its 3 x 3 columns at
+// spacing 1 (F1) and at spacing 2 (F2), the raw values of the next planes
+// and the node's moments loaded one plane ahead.
+template <class PR, bool GC>
 __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
-  const BoxDesc& b = boxes[box0 + blockIdx.y];
-  const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
-  double* aux = b.aux;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    int x, y, z;
-    node_xyz(b, i, x, y, z);
-    double rho, u[3], phi, p, ps;
-    bool fin;
-    node_obs<PR>(b, parity, x, y, z, rho, u, phi, p, ps, fin);
-    double g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
-    for (int cz = -1; cz <= 1; ++cz)
-      for (int cy = -1; cy <= 1; ++cy)
-        for (int cx = -1; cx <= 1; ++cx) {
-          if (cx == 0 && cy == 0 && cz == 0) continue;
-          const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
-          const double v1 = phi_node<PR>(b, parity, map_axis(x + cx, b.nx, b.wall[0]), map_axis(y + cy, b.ny, b.wall[1]),
-                                         map_axis(z + cz, b.nz, b.wall[2]));
-          const double v2 = phi_node<PR>(b, parity, map_axis(x + 2 * cx, b.nx, b.wall[0]),
-                                         map_axis(y + 2 * cy, b.ny, b.wall[1]), map_axis(z + 2 * cz, b.nz, b.wall[2]));
-          const double c[3] = {double(cx), double(cy), double(cz)};
-          for (int a = 0; a < 3; ++a) {
-            g1[a] += 3.0 * w * c[a] * v1;
-            g2[a] += 1.5 * w * c[a] * v2;
-          }
-        }
-    double g[3];
-    for (int a = 0; a < 3; ++a) g[a] = (4.0 * g1[a] - g2[a]) / 3.0;
-    const double inv = 1.0 / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + 1e-12);
-    const double pp = phi * (1.0 - phi);
-    for (int a = 0; a < 3; ++a) {
-      aux[a * n + i] = u[a];
-      aux[(3 + a) * n + i] = pp * g[a] * inv;
-    }
-  }
-}
-
-template <class PR>
-__global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
+  using TM = typename PR::TM;
   using TP = typename PR::TP;
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   const int nx = b.nx, ny = b.ny, nz = b.nz;
   const int64_t n = static_cast<int64_t>(nx) * ny * nz;
-  const double* aux = b.aux;
-  const bool literal = (b.flags & 1) != 0;
-  const double kac = b.kappa_ac, mob = b.mobility;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    int x, y, z;
-    node_xyz(b, i, x, y, z);
-    const double phi0 = phi_node<PR>(b, parity, x, y, z);
-    double adv[2] = {0, 0}, shp[2] = {0, 0}, lap[2] = {0, 0}, g[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    for (int cz = -1; cz <= 1; ++cz)
-      for (int cy = -1; cy <= 1; ++cy)
-        for (int cx = -1; cx <= 1; ++cx) {
-          if (cx == 0 && cy == 0 && cz == 0) continue;
-          const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
-          const double c[3] = {double(cx), double(cy), double(cz)};
-          for (int s = 1; s <= 2; ++s) {
-            int kx, ky, kz;
-            const int xm = map_axis(x + s * cx, nx, b.wall[0], kx);
-            const int ym = map_axis(y + s * cy, ny, b.wall[1], ky);
-            const int zm = map_axis(z + s * cz, nz, b.wall[2], kz);
-            const int64_t j = (static_cast<int64_t>(zm) * ny + ym) * nx + xm;
-            const double ph = phi_node<PR>(b, parity, xm, ym, zm);
-            const double su = ((kx + ky + kz) & 1) ? -1.0 : 1.0;
-            const double sn[3] = {kx ? -1.0 : 1.0, ky ? -1.0 : 1.0, kz ? -1.0 : 1.0};
-            double uc = 0, sc = 0;
-            for (int a = 0; a < 3; ++a) {
-              uc += c[a] * aux[a * n + j];
-              sc += c[a] * sn[a] * aux[(3 + a) * n + j];
-            }
-            const double wt = 3.0 * w / s;
-            adv[s - 1] += wt * ph * su * uc;
-            shp[s - 1] += wt * sc;
-            lap[s - 1] += (6.0 * w / (s * s)) * (ph - phi0);
-            for (int a = 0; a < 3; ++a) g[s - 1][a] += wt * c[a] * ph;
-          }
-        }
-    auto four = [](const double* v) { return (4.0 * v[0] - v[1]) / 3.0; };
-    double a_term;
-    if (literal) {
-      a_term = 0.0;
-      for (int a = 0; a < 3; ++a) a_term += aux[a * n + i] * (4.0 * g[0][a] - g[1][a]) / 3.0;
-    } else {
-      a_term = four(adv);
+  const int64_t ncol = static_cast<int64_t>(nx) * ny;
+  const int64_t units = ncol * ((nz + kHoZ - 1) / kHoZ);
+  const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
+  const gptr<const TM> fmom = (gptr<const TM>)b.mom[parity];
+  double* __restrict__ aux = b.aux;
+  constexpr int NMOM = GC ? 4 : 10;
+  for (int64_t un = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; un < units;
+       un += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t col = un % ncol;
+    const int x = static_cast<int>(col % nx), y = static_cast<int>(col / nx);
+    const int z0 = static_cast<int>(un / ncol) * kHoZ, z1 = min(z0 + kHoZ, nz);
+    int xs[3], ys[3], kx[3], ky[3], xs2[3], ys2[3];
+    for (int c = -1; c <= 1; ++c) {
+      xs[c + 1] = map_axis(x + c, nx, b.wall[0], kx[c + 1]);
+      ys[c + 1] = map_axis(y + c, ny, b.wall[1], ky[c + 1]);
+      xs2[c + 1] = map_axis(x + 2 * c, nx, b.wall[0]);
+      ys2[c + 1] = map_axis(y + 2 * c, ny, b.wall[1]);
     }
-    const double phin = phi0 - a_term + mob * four(lap) - kac * four(shp);
+    TP r1[9], r2[9];
+    TM rm[NMOM];
+    auto issue1 = [&](int q) {
+      const int zq = map_axis(q, nz, b.wall[2]);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) r1[k] = fphi[phi_at(b, xs[k % 3], ys[k / 3], zq)];
+    };
+    auto issue2 = [&](int q) {
+      const int zq = map_axis(q, nz, b.wall[2]);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) r2[k] = fphi[phi_at(b, xs2[k % 3], ys2[k / 3], zq)];
+    };
+    auto issue_mom = [&](int zm) {
+#pragma unroll
+      for (int k = 0; k < NMOM; ++k) rm[k] = fmom[mom_at(b, k, x, y, zm)];
+    };
+    auto filt = [&](const TP* r, double F[4]) {
+      auto ld = [&](int, int, int cx, int cy) { return dec<double>(r[cy * 3 + cx], 0.f, 1.f); };
+      diag_filter(ld, xs, ys, F);
+    };
+    auto filter_J = [&](int q, double JF[3][4]) {
+      int kz;
+      const int zq = map_axis(q, nz, b.wall[2], kz);
+      for (int a = 0; a < 3; ++a) {
+        auto ldj = [&](int xm, int ym, int cx, int cy) {
+          const double v = dec<double>(fmom[mom_at(b, 1 + a, xm, ym, zq)], b.enc_off[1 + a], b.enc_inv[1 + a]);
+          return ((kx[cx] + ky[cy] + kz) & 1) ? -v : v;
+        };
+        diag_filter(ldj, xs, ys, JF[a]);
+      }
+    };
+    // F1 of planes z-1, z, z+1; F2 of planes z-2 .. z+2
+    double F1[3][4], F2[5][4];
+    double JFm[GC ? 3 : 1][4], JF0[GC ? 3 : 1][4], JFn[GC ? 3 : 1][4];
+    issue1(z0 - 1);
+    filt(r1, F1[0]);
+    issue1(z0);
+    filt(r1, F1[1]);
+    for (int k = 0; k < 4; ++k) {
+      issue2(z0 - 2 + k);
+      filt(r2, F2[k]);
+    }
+    if constexpr (GC) {
+      filter_J(z0 - 1, JFm);
+      filter_J(z0, JF0);
+    }
+    issue1(z0 + 1);
+    issue2(z0 + 2);
+    issue_mom(z0);
+    for (int z = z0; z < z1; ++z) {
+      filt(r1, F1[2]);  // plane z + 1
+      filt(r2, F2[4]);  // plane z + 2
+      if constexpr (GC) filter_J(z + 1, JFn);
+      double m[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < NMOM; ++k) m[k] = dec<double>(rm[k], b.enc_off[k], b.enc_inv[k]);
+      if (z + 1 < z1) {
+        issue1(z + 2);
+        issue2(z + 3);
+        issue_mom(z + 1);
+      }
+      const double phi = F1[1][3];
+      const double g[3] = {(F1[0][1] + 4.0 * F1[1][1] + F1[2][1]) * (1.0 / 72.0),
+                           (F1[0][2] + 4.0 * F1[1][2] + F1[2][2]) * (1.0 / 72.0), (F1[2][0] - F1[0][0]) * (1.0 / 72.0)};
+      const double lap = (F1[0][0] + 4.0 * F1[1][0] + F1[2][0]) * (1.0 / 36.0) - 6.0 * phi;
+      const double g2[3] = {(F2[0][1] + 4.0 * F2[2][1] + F2[4][1]) * (1.0 / 144.0),
+                            (F2[0][2] + 4.0 * F2[2][2] + F2[4][2]) * (1.0 / 144.0),
+                            (F2[4][0] - F2[0][0]) * (1.0 / 144.0)};
+      // u = J + a/2 with the second-order forces of Sec. II.C (node_obs)
+      const double phic = fmin(fmax(phi, 0.0), 1.0);
+      const double rho = b.rho_g + phic * b.drho;
+      const double nu = b.nu_g + phic * b.dnu;
+      const double om = 1.0 / (3.0 * nu + 0.5);
+      const double mu = b.beta4 * phi * (phi - 1.0) * (phi - 0.5) - b.kappa_mu * lap;
+      const double P = m[0];
+      double Q[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+      if constexpr (GC) {
+        double gJ[3][3];
+        for (int a = 0; a < 3; ++a) {
+          gJ[a][0] = (JFm[a][1] + 4.0 * JF0[a][1] + JFn[a][1]) * (1.0 / 72.0);
+          gJ[a][1] = (JFm[a][2] + 4.0 * JF0[a][2] + JFn[a][2]) * (1.0 / 72.0);
+          gJ[a][2] = (JFn[a][0] - JFm[a][0]) * (1.0 / 72.0);
+        }
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) Q[a][c] = -(1.0 / 3.0) / om * (gJ[a][c] + gJ[c][a]);
+      }
+      double g4[3];
+      for (int a = 0; a < 3; ++a) g4[a] = (4.0 * g[a] - g2[a]) / 3.0;
+      const double inv = 1.0 / (sqrt(g4[0] * g4[0] + g4[1] * g4[1] + g4[2] * g4[2]) + 1e-12);
+      const double pp = phi * (1.0 - phi);
+      const int64_t i = (static_cast<int64_t>(z) * ny + y) * nx + x;
+      for (int a = 0; a < 3; ++a) {
+        double qg = 0;
+        for (int c = 0; c < 3; ++c) qg += Q[a][c] * g[c] * b.drho;
+        const double F = mu * g[a] - P * (1.0 / 3.0) * b.drho * g[a] - 3.0 * nu * om * qg +
+                         (rho - b.rho_ref) * b.grav[a];
+        aux[a * n + i] = m[1 + a] + 0.5 * F / rho;
+        aux[(3 + a) * n + i] = pp * g4[a] * inv;
+      }
+      for (int k = 0; k < 4; ++k) {
+        F1[0][k] = F1[1][k];
+        F1[1][k] = F1[2][k];
+        for (int p = 0; p < 4; ++p) F2[p][k] = F2[p + 1][k];
+      }
+      if constexpr (GC)
+        for (int a = 0; a < 3; ++a)
+          for (int k = 0; k < 4; ++k) {
+            JFm[a][k] = JF0[a][k];
+            JF0[a][k] = JFn[a][k];
+          }
+    }
+  }
+}
+
+// The phase update.  A workgroup of 256 threads owns a tile of kHoTX x kHoTY
+// output columns and marches it over up to kHoZ planes.  Per plane it stages,
+// with a two-column halo, the flux G = phi u + (4M/W) S (only (4M/W) S for
+// the printed advection) and phi in LDS, ghost rules applied as the values
+// are staged; each thread then filters its column in x and y at spacings 1
+// and 2 from LDS and keeps the filtered values of planes z-2 .. z+2 in
+// registers.  With plane z+2 staged, output plane z is complete.
+constexpr int kHoTX = 32, kHoTY = 8;
+constexpr int kHoPX = kHoTX + 4, kHoPY = kHoTY + 4, kHoNP = kHoPX * kHoPY;
+constexpr int kHoPer = (kHoNP + 255) / 256;  // staged elements per thread
+
+// LIT: the boxes advect phi with the printed u . grad(phi) (every box of a
+// launch alike); only then are the x and y differences of phi carried.
+template <class PR, bool LIT>
+__global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
+  using TP = typename PR::TP;
+  constexpr int NV = LIT ? 6 : 4;  // filtered values per plane
+  __shared__ double sG[3][kHoNP];
+  __shared__ double sP[kHoNP];
+  const BoxDesc& b = boxes[box0 + blockIdx.y];
+  const int nx = b.nx, ny = b.ny, nz = b.nz;
+  const int ntx = (nx + kHoTX - 1) / kHoTX, nty = (ny + kHoTY - 1) / kHoTY;
+  const int tiles = ntx * nty * ((nz + kHoZ - 1) / kHoZ);
+  if (static_cast<int>(blockIdx.x) >= tiles) return;  // uniform: boxes have different tile counts
+  const int t = blockIdx.x;
+  const int x0 = (t % ntx) * kHoTX, y0 = ((t / ntx) % nty) * kHoTY, z0 = (t / (ntx * nty)) * kHoZ;
+  const int z1 = min(z0 + kHoZ, nz);
+  const int64_t n = static_cast<int64_t>(nx) * ny * nz;
+  const double* __restrict__ aux = b.aux;
+  const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
+  const double kac = b.kappa_ac, mob = b.mobility;
+  const int tid = threadIdx.x;
+  const int lx = tid % kHoTX, ly = tid / kHoTX;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool active = x < nx && y < ny;
+  // staged elements of this thread: mapped column and crossing flags
+  int ecol[kHoPer], ex[kHoPer], ey[kHoPer], ekx[kHoPer], eky[kHoPer];
+  for (int j = 0; j < kHoPer; ++j) {
+    const int e = tid + 256 * j;
+    const int ee = e < kHoNP ? e : 0;
+    ex[j] = map_axis(x0 - 2 + ee % kHoPX, nx, b.wall[0], ekx[j]);
+    ey[j] = map_axis(y0 - 2 + ee / kHoPX, ny, b.wall[1], eky[j]);
+    ecol[j] = ey[j] * nx + ex[j];
+  }
+  auto stage = [&](int q) {
+    int kz;
+    const int zq = map_axis(q, nz, b.wall[2], kz);
+    for (int j = 0; j < kHoPer; ++j) {
+      const int e = tid + 256 * j;
+      if (e >= kHoNP) continue;
+      const int64_t i = static_cast<int64_t>(zq) * nx * ny + ecol[j];
+      const double ph = dec<double>(fphi[phi_at(b, ex[j], ey[j], zq)], 0.f, 1.f);
+      const double su = ((ekx[j] + eky[j] + kz) & 1) ? -1.0 : 1.0;
+      const double r[3] = {ekx[j] ? -1.0 : 1.0, eky[j] ? -1.0 : 1.0, kz ? -1.0 : 1.0};
+      const double pa = LIT ? 0.0 : su * ph;
+      for (int a = 0; a < 3; ++a) sG[a][e] = pa * aux[a * n + i] + kac * (r[a] * aux[(3 + a) * n + i]);
+      sP[e] = ph;
+    }
+  };
+  // filtered values of one plane at this thread's column, spacing s:
+  // v[0] = sum_cy w(cy) (Gx(+s, cy) - Gx(-s, cy)), v[1] likewise for Gy
+  // along y, v[2] = sum w w Gz, v[3] = sum w w phi, v[4], v[5] = the
+  // x and y differences of phi (printed advection)
+  auto filt = [&](int s, double* v) {
+    const int c0 = (ly + 2) * kHoPX + lx + 2;
+    double hx = 0, hy = 0, hz = 0, L = 0, dx = 0, dy = 0;
+    for (int cy = -1; cy <= 1; ++cy)
+      for (int cx = -1; cx <= 1; ++cx) {
+        const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0);
+        const int e = c0 + s * (cy * kHoPX + cx);
+        hx += w * cx * sG[0][e];
+        hy += w * cy * sG[1][e];
+        hz += w * sG[2][e];
+        L += w * sP[e];
+        if constexpr (LIT) {
+          dx += w * cx * sP[e];
+          dy += w * cy * sP[e];
+        }
+      }
+    v[0] = hx;
+    v[1] = hy;
+    v[2] = hz;
+    v[3] = L;
+    if constexpr (LIT) {
+      v[4] = dx;
+      v[5] = dy;
+    }
+  };
+  // rings of the last staged planes: V1 at spacing 1 for planes z-1 .. z+2
+  // (index 0 .. 3; z-1, z, z+1 used), V2 at spacing 2 for planes z-2 .. z+2
+  // (index 0 .. 4; z-2, z, z+2 used); PC: phi at the column for planes z,
+  // z+1, z+2
+  double V1[4][NV], V2[5][NV], PC[3];
+  for (int q = z0 - 2; q <= z1 + 1; ++q) {
+    stage(q);
+    __syncthreads();
+    const int k1 = q - (z0 - 2);  // planes staged so far - 1
+    {
+      double v1[NV], v2[NV];
+      filt(1, v1);
+      filt(2, v2);
+      const double pc = sP[(ly + 2) * kHoPX + lx + 2];
+      // shift the rings and append plane q
+      for (int k = 0; k < NV; ++k) {
+        for (int p = 0; p < 3; ++p) V1[p][k] = V1[p + 1][k];
+        for (int p = 0; p < 4; ++p) V2[p][k] = V2[p + 1][k];
+        V1[3][k] = v1[k];
+        V2[4][k] = v2[k];
+      }
+      PC[0] = PC[1];
+      PC[1] = PC[2];
+      PC[2] = pc;
+    }
+    __syncthreads();
+    if (k1 < 4) continue;  // output plane z = q - 2 needs planes z-2 .. z+2
+    const int z = q - 2;
+    if (!active) continue;
+    const double phi = PC[0];
+    const double div1 = (V1[0][0] + 4.0 * V1[1][0] + V1[2][0]) + (V1[0][1] + 4.0 * V1[1][1] + V1[2][1]) +
+                        (V1[2][2] - V1[0][2]);
+    const double div2 = (V2[0][0] + 4.0 * V2[2][0] + V2[4][0]) + (V2[0][1] + 4.0 * V2[2][1] + V2[4][1]) +
+                        (V2[4][2] - V2[0][2]);
+    const double lap1 = (V1[0][3] + 4.0 * V1[1][3] + V1[2][3]) * (1.0 / 36.0) - 6.0 * phi;
+    const double lap2 = (V2[0][3] + 4.0 * V2[2][3] + V2[4][3]) * (1.0 / 144.0) - 1.5 * phi;
+    const double div4 = (4.0 * div1 * (1.0 / 72.0) - div2 * (1.0 / 144.0)) / 3.0;
+    const double lap4 = (4.0 * lap1 - lap2) / 3.0;
+    double adv = 0.0;
+    if constexpr (LIT) {
+      const int64_t i = (static_cast<int64_t>(z) * ny + y) * nx + x;
+      const double g1[3] = {(V1[0][4] + 4.0 * V1[1][4] + V1[2][4]) * (1.0 / 72.0),
+                            (V1[0][5] + 4.0 * V1[1][5] + V1[2][5]) * (1.0 / 72.0), (V1[2][3] - V1[0][3]) * (1.0 / 72.0)};
+      const double g2[3] = {(V2[0][4] + 4.0 * V2[2][4] + V2[4][4]) * (1.0 / 144.0),
+                            (V2[0][5] + 4.0 * V2[2][5] + V2[4][5]) * (1.0 / 144.0),
+                            (V2[4][3] - V2[0][3]) * (1.0 / 144.0)};
+      for (int a = 0; a < 3; ++a) adv += aux[a * n + i] * (4.0 * g1[a] - g2[a]) / 3.0;
+    }
+    const double phin = phi - adv - div4 + mob * lap4;
     ((gptr<TP>)b.phi[1 - parity])[phi_at(b, x, y, z)] = Enc<TP>::go(phin, 0.f, 1.f);
   }
 }
@@ -613,19 +806,32 @@ hipError_t launch_observable(int precision, const BoxDesc& box, int parity, int 
 }
 
 int high_order_blocks_per_box(int64_t max_nodes) {
-  int64_t nb = (max_nodes + 256 * 4 - 1) / (256 * 4);
-  return static_cast<int>(nb < 1 ? 1 : (nb > 8192 ? 8192 : nb));
+  int64_t nb = (max_nodes + 256 * 16 - 1) / (256 * 16);
+  return static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
 }
 
-hipError_t launch_high_order_phase(int precision, const BoxDesc* d_boxes, int box0, int nbox, int parity,
-                                   int blocks_per_box, hipStream_t stream) {
-  if (nbox <= 0 || blocks_per_box <= 0) return hipErrorInvalidValue;
+int high_order_phase_tiles(int nx, int ny, int nz) {
+  return ((nx + kHoTX - 1) / kHoTX) * ((ny + kHoTY - 1) / kHoTY) * ((nz + kHoZ - 1) / kHoZ);
+}
+
+hipError_t launch_high_order_phase(int precision, bool gc, bool literal, const BoxDesc* d_boxes, int box0, int nbox,
+                                   int parity, int flux_blocks, int phase_tiles, hipStream_t stream) {
+  if (nbox <= 0 || flux_blocks <= 0 || phase_tiles <= 0) return hipErrorInvalidValue;
   return dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
-    hipLaunchKernelGGL((ho_flux_kernel<PR>), dim3(blocks_per_box, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    if (gc)
+      hipLaunchKernelGGL((ho_flux_kernel<PR, true>), dim3(flux_blocks, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    else
+      hipLaunchKernelGGL((ho_flux_kernel<PR, false>), dim3(flux_blocks, nbox), dim3(256), 0, stream, d_boxes, box0,
+                         parity);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((ho_phase_kernel<PR>), dim3(blocks_per_box, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    if (literal)
+      hipLaunchKernelGGL((ho_phase_kernel<PR, true>), dim3(phase_tiles, nbox), dim3(256), 0, stream, d_boxes, box0,
+                         parity);
+    else
+      hipLaunchKernelGGL((ho_phase_kernel<PR, false>), dim3(phase_tiles, nbox), dim3(256), 0, stream, d_boxes, box0,
+                         parity);
     return hipGetLastError();
   });
 }

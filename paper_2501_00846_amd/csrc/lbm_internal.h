@@ -64,12 +64,16 @@ void default_encoding(double off[10], double scale[10]);
 void fill_box_desc(const lbm_params& p, int precision, const double off[10], const double scale[10], BoxDesc& d);
 
 // Fourth-order phase-field update of boxes box0 .. box0 + nbox - 1 (every
-// one with LBM_HIGH_ORDER_AC and its aux planes): reads state `parity`,
-// overwrites phi of buffer 1 - parity.  Runs after the fused step of the same
-// parity; blocks_per_box workgroups share each box.
-hipError_t launch_high_order_phase(int precision, const BoxDesc* d_boxes, int box0, int nbox, int parity,
-                                   int blocks_per_box, hipStream_t stream);
+// one with LBM_HIGH_ORDER_AC and its aux planes; gc: they use the gradient
+// closure; literal: they advect with the printed u . grad(phi)): reads state
+// `parity`, overwrites phi of buffer 1 - parity.  Runs after the fused step of
+// the same parity.  flux_blocks: workgroups per box of the flux kernel
+// (high_order_blocks_per_box of the largest box); phase_tiles: the largest
+// high_order_phase_tiles over the boxes.
+hipError_t launch_high_order_phase(int precision, bool gc, bool literal, const BoxDesc* d_boxes, int box0, int nbox,
+                                   int parity, int flux_blocks, int phase_tiles, hipStream_t stream);
 int high_order_blocks_per_box(int64_t max_nodes);
+int high_order_phase_tiles(int nx, int ny, int nz);
 
 constexpr int kDiagValues = 28;
 constexpr int kDiagBlocks = 1024;

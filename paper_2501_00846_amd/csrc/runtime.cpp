@@ -45,7 +45,9 @@ struct lbm_ctx {
   int precision = 0;
   bool gc = false;  // LBM_GRADIENT_CLOSURE (all boxes)
   bool ho = false;  // LBM_HIGH_ORDER_AC (all boxes)
-  int ho_bpb = 1;   // workgroups per box of the fourth-order phase kernels
+  bool ho_lit = false;  // with LBM_HIGH_ORDER_AC: LBM_LITERAL_ADVECTION (all boxes)
+  int ho_bpb = 1;   // workgroups per box of the fourth-order flux kernel
+  int ho_tiles = 1; // workgroups per box of the fourth-order phase kernel (largest box)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   lbm_device dev{};
@@ -216,8 +218,8 @@ hipError_t enqueue_steps(lbm_ctx* c, int nsteps, int parity0) {
                                      c->d_items, c->n_items, grid, parity, c->stream);
     if (e != hipSuccess) return e;
     if (c->ho) {
-      e = lbm::launch_high_order_phase(c->precision, c->d_boxes, 0, static_cast<int>(c->boxes.size()), parity,
-                                       c->ho_bpb, c->stream);
+      e = lbm::launch_high_order_phase(c->precision, c->gc, c->ho_lit, c->d_boxes, 0, static_cast<int>(c->boxes.size()),
+                                       parity, c->ho_bpb, c->ho_tiles, c->stream);
       if (e != hipSuccess) return e;
     }
     parity ^= 1;
@@ -406,6 +408,9 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
         return fail(nullptr, LBM_ERR_UNSUPPORTED, "lbm_create: box %d: all boxes of a context must share one closure", i);
       if ((boxes[i].flags ^ boxes[0].flags) & LBM_HIGH_ORDER_AC)
         return fail(nullptr, LBM_ERR_UNSUPPORTED, "lbm_create: box %d: all boxes of a context must share LBM_HIGH_ORDER_AC", i);
+      if ((boxes[0].flags & LBM_HIGH_ORDER_AC) && ((boxes[i].flags ^ boxes[0].flags) & LBM_LITERAL_ADVECTION))
+        return fail(nullptr, LBM_ERR_UNSUPPORTED,
+                    "lbm_create: box %d: with LBM_HIGH_ORDER_AC all boxes must share LBM_LITERAL_ADVECTION", i);
     }
     if (dev && ((dev->alloc == nullptr) != (dev->free == nullptr)))
       return fail(nullptr, LBM_ERR_ARG, "lbm_create: alloc and free callbacks must be given together");
@@ -415,6 +420,7 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
     c->precision = boxes[0].precision;
     c->gc = (boxes[0].flags & LBM_GRADIENT_CLOSURE) != 0;
     c->ho = (boxes[0].flags & LBM_HIGH_ORDER_AC) != 0;
+    c->ho_lit = c->ho && (boxes[0].flags & LBM_LITERAL_ADVECTION) != 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) {
       delete c;
@@ -463,6 +469,8 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
     for (auto& b : c->boxes) max_n = std::max(max_n, b.n);
     c->diag_bpb = lbm::diag_blocks_per_box(max_n);
     c->ho_bpb = lbm::high_order_blocks_per_box(max_n);
+    for (auto& b : c->boxes)
+      c->ho_tiles = std::max(c->ho_tiles, lbm::high_order_phase_tiles(b.prm.nx, b.prm.ny, b.prm.nz));
     c->d_diag = static_cast<double*>(dev_alloc(
         c, align256(static_cast<size_t>(n_boxes) * (c->diag_bpb + 1) * lbm::kDiagValues * sizeof(double))));
     if (!c->d_boxes || !c->d_diag) {
@@ -595,8 +603,8 @@ lbm_status lbm_step_unbatched(lbm_ctx* c, int32_t nsteps) {
       HIP_TRY(c, lbm::launch_fused(c->precision, c->gc, c->tuning.block_x, c->tuning.block_y, c->d_boxes,
                                    c->d_items + bi.first, bi.second, bi.second, c->parity, c->stream));
       if (c->ho)
-        HIP_TRY(c, lbm::launch_high_order_phase(c->precision, c->d_boxes, static_cast<int>(k), 1, c->parity,
-                                                c->ho_bpb, c->stream));
+        HIP_TRY(c, lbm::launch_high_order_phase(c->precision, c->gc, c->ho_lit, c->d_boxes, static_cast<int>(k), 1,
+                                                c->parity, c->ho_bpb, c->ho_tiles, c->stream));
     }
     c->parity ^= 1;
   }

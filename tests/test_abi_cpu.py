@@ -177,3 +177,5 @@ def test_high_order_variant_needs_four_nodes_on_wall_axes():
     st, _, msg = _create([p2, _params()])
     assert st == -2 and "LBM_HIGH_ORDER_AC" in msg
     assert _noalloc(p3)[0] == -2
+    st, _, msg = _create([_params(flags=4), _params(flags=5)])  # printed advection in one box only
+    assert st == -2 and "LBM_LITERAL_ADVECTION" in msg
