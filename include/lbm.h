@@ -285,9 +285,12 @@ int64_t lbm_total_nodes(const lbm_ctx* ctx);
  *   phi[s]: nz*ny*pitch elements, FP64 in LBM_FP64 else FP32; node (x, y, z)
  *     at (z*ny + y)*pitch + x;
  *   mom[s]: nz*nmom*ny*pitch elements, FP64 / FP32 / IEEE binary16 / bfloat16
- *     by precision; moment k of node (x, y, z) at ((z*nmom + k)*ny + y)*pitch + x,
- *     k over P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz (nmom = 10), or P, J
- *     (nmom = 4) with LBM_GRADIENT_CLOSURE; the 16-bit modes store
+ *     by precision, k over P, Jx, Jy, Jz, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
+ *     (nmom = 10), or P, J (nmom = 4) with LBM_GRADIENT_CLOSURE.  FP64 and
+ *     FP32: moment k of node (x, y, z) at ((z*nmom + k)*ny + y)*pitch + x.
+ *     16-bit modes: moments in pairs (k = 2p, 2p + 1), one 32-bit word per
+ *     node and pair with the even field in the low half, moment k at 16-bit
+ *     element 2*(((z*nmom/2 + k/2)*ny + y)*pitch + x) + k%2; each stores
  *     (value - enc_offset[k]) * enc_scale[k].
  *   Elements x >= nx of a row are never read or written.
  * enc_offset, enc_scale: 10 values each (rules of lbm_set_encoding) or both

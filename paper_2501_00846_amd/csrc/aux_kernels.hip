@@ -22,8 +22,18 @@ namespace {
 __device__ __forceinline__ int64_t phi_at(const BoxDesc& b, int x, int y, int z) {
   return (static_cast<int64_t>(z) * b.ny + y) * b.pitch + x;
 }
+// Element index of moment k of node (x, y, z) in the moment array of element
+// type TM.  FP64 / FP32: plane k of the node's z plane.  16-bit storage: the
+// moments are kept in pairs, (P, Jx), (Jy, Jz), (Qxx, Qyy), (Qzz, Qxy),
+// (Qxz, Qyz) (P, J only with the gradient closure), one 32-bit word per node
+// and pair with the even field in the low half (little-endian: the lower
+// element index).
+template <class TM>
 __device__ __forceinline__ int64_t mom_at(const BoxDesc& b, int k, int x, int y, int z) {
-  return ((static_cast<int64_t>(z) * b.nmom + k) * b.ny + y) * b.pitch + x;
+  if constexpr (sizeof(TM) == 2)
+    return 2 * (((static_cast<int64_t>(z) * (b.nmom / 2) + k / 2) * b.ny + y) * b.pitch + x) + (k & 1);
+  else
+    return ((static_cast<int64_t>(z) * b.nmom + k) * b.ny + y) * b.pitch + x;
 }
 // coordinates of the flat node index i = x + nx (y + ny z)
 // (32-bit divisions whenever the index fits, which covers boxes of up to
@@ -56,7 +66,7 @@ __global__ void encode_kernel(BoxDesc b, int parity, int field, const double* __
     } else {
       const int k = field - 1;
       if (k < b.nmom)  // Q is not stored by the gradient closure
-        ((gptr<TM>)b.mom[parity])[mom_at(b, k, x, y, z)] = Enc<TM>::go(src[i], b.enc_off[k], b.enc_scale[k]);
+        ((gptr<TM>)b.mom[parity])[mom_at<TM>(b, k, x, y, z)] = Enc<TM>::go(src[i], b.enc_off[k], b.enc_scale[k]);
     }
   }
 }
@@ -73,7 +83,7 @@ __global__ void decode_kernel(BoxDesc b, int parity, int field, double* __restri
       dst[i] = dec<double>(((gptr<const TP>)b.phi[parity])[phi_at(b, x, y, z)], 0.f, 1.f);
     } else {
       const int k = field - 1;
-      dst[i] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_at(b, k, x, y, z)], b.enc_off[k], b.enc_inv[k])
+      dst[i] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_at<TM>(b, k, x, y, z)], b.enc_off[k], b.enc_inv[k])
                           : 0.0;
     }
   }
@@ -90,7 +100,7 @@ __global__ void gather_kernel(BoxDesc b, int parity, const int64_t* __restrict__
     node_xyz(b, idx[j], x, y, z);
     out[j] = dec<double>(((gptr<const TP>)b.phi[parity])[phi_at(b, x, y, z)], 0.f, 1.f);
     for (int k = 0; k < 10; ++k)
-      out[(k + 1) * n + j] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_at(b, k, x, y, z)],
+      out[(k + 1) * n + j] = k < b.nmom ? dec<double>(((gptr<const TM>)b.mom[parity])[mom_at<TM>(b, k, x, y, z)],
                                                       b.enc_off[k], b.enc_inv[k])
                                         : 0.0;
   }
@@ -116,7 +126,7 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
     for (int k = 0; k < 10; ++k) m[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < NMOM; ++k) {
-      m[k] = dec<double>(fmom[mom_at(b, k, x, y, z)], b.enc_off[k], b.enc_inv[k]);
+      m[k] = dec<double>(fmom[mom_at<TM>(b, k, x, y, z)], b.enc_off[k], b.enc_inv[k]);
       finite = finite && isfinite(m[k]);
     }
   };
@@ -156,15 +166,14 @@ __device__ void node_obs(const BoxDesc& b, int parity, int x, int y, int z, doub
     // gradient closure: the viscous correction contracts -(cs^2/omega)(grad J + grad J^T),
     // J ghosts minus the mirrored value per wall crossed
     double gJ[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    const int64_t fstride = static_cast<int64_t>(ny) * b.pitch;  // one moment plane
     for (int cz = -1; cz <= 1; ++cz)
       for (int cy = -1; cy <= 1; ++cy) {
-        const gptr<const TM> rowJ = fmom + mom_at(b, 1, 0, ys[cy + 1], zs[cz + 1]);
         for (int cx = -1; cx <= 1; ++cx) {
           const double sgn = ((kxs[cx + 1] + kys[cy + 1] + kzs[cz + 1]) & 1) ? -1.0 : 1.0;
           const double w = 3.0 * (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0) * (cz ? 1.0 : 4.0) / 216.0;
           for (int a = 0; a < 3; ++a) {
-            const double ja = sgn * dec<double>(rowJ[a * fstride + xs[cx + 1]], b.enc_off[1 + a], b.enc_inv[1 + a]);
+            const double ja = sgn * dec<double>(fmom[mom_at<TM>(b, 1 + a, xs[cx + 1], ys[cy + 1], zs[cz + 1])],
+                                                b.enc_off[1 + a], b.enc_inv[1 + a]);
             gJ[a][0] += w * cx * ja;
             gJ[a][1] += w * cy * ja;
             gJ[a][2] += w * cz * ja;
@@ -302,7 +311,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const BoxDes
     };
     auto issue_mom = [&](int zm) {
 #pragma unroll
-      for (int k = 0; k < NMOM; ++k) rm[k] = fmom[mom_at(b, k, x, y, zm)];
+      for (int k = 0; k < NMOM; ++k) rm[k] = fmom[mom_at<TM>(b, k, x, y, zm)];
     };
     auto filter_phi = [&](double F[4]) {
       auto ld = [&](int, int, int cx, int cy) { return dec<double>(rph[cy * 3 + cx], 0.f, 1.f); };
@@ -315,7 +324,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const BoxDes
       const int zq = map_axis(q, nz, b.wall[2], kz);
       for (int a = 0; a < 3; ++a) {
         auto ldj = [&](int xm, int ym, int cx, int cy) {
-          const double v = dec<double>(fmom[mom_at(b, 1 + a, xm, ym, zq)], b.enc_off[1 + a], b.enc_inv[1 + a]);
+          const double v = dec<double>(fmom[mom_at<TM>(b, 1 + a, xm, ym, zq)], b.enc_off[1 + a], b.enc_inv[1 + a]);
           return ((kx[cx] + ky[cy] + kz) & 1) ? -v : v;
         };
         diag_filter(ldj, xs, ys, JF[a]);
@@ -512,7 +521,7 @@ __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict_
     };
     auto issue_mom = [&](int zm) {
 #pragma unroll
-      for (int k = 0; k < NMOM; ++k) rm[k] = fmom[mom_at(b, k, x, y, zm)];
+      for (int k = 0; k < NMOM; ++k) rm[k] = fmom[mom_at<TM>(b, k, x, y, zm)];
     };
     auto filt = [&](const TP* r, double F[4]) {
       auto ld = [&](int, int, int cx, int cy) { return dec<double>(r[cy * 3 + cx], 0.f, 1.f); };
@@ -523,7 +532,7 @@ __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict_
       const int zq = map_axis(q, nz, b.wall[2], kz);
       for (int a = 0; a < 3; ++a) {
         auto ldj = [&](int xm, int ym, int cx, int cy) {
-          const double v = dec<double>(fmom[mom_at(b, 1 + a, xm, ym, zq)], b.enc_off[1 + a], b.enc_inv[1 + a]);
+          const double v = dec<double>(fmom[mom_at<TM>(b, 1 + a, xm, ym, zq)], b.enc_off[1 + a], b.enc_inv[1 + a]);
           return ((kx[cx] + ky[cy] + kz) & 1) ? -v : v;
         };
         diag_filter(ldj, xs, ys, JF[a]);

@@ -219,6 +219,20 @@ struct FusedShared {
   R gg[3 * NT];
 };
 
+// 16-bit storage keeps the moments in pairs: one 32-bit word per node holds
+// fields 2p (low half) and 2p + 1 (high half) of pair plane p, so that a step
+// issues half as many moment loads and stores (a wave's store costs the
+// vector memory path about the same for 2- and 4-byte elements).
+template <class TM>
+__device__ __forceinline__ TM half_of(uint32_t w, int hi) {
+  return __builtin_bit_cast(TM, static_cast<uint16_t>(hi ? (w >> 16) : w));
+}
+template <class TM>
+__device__ __forceinline__ uint32_t pack_pair(TM lo, TM hi) {
+  return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, lo)) |
+         (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hi)) << 16);
+}
+
 // ---------------------------------------------------------------------------
 // The fused step
 // ---------------------------------------------------------------------------
@@ -247,9 +261,10 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
   constexpr int PY = BY + 2;
   constexpr int NM = GC ? 4 : 10;  // moment fields per plane
   constexpr int NL = GC ? 1 : 10;  // of them loaded per lane (the closure takes J from its LDS patch)
-  // non-temporal output stores possible: FP64 / FP32 storage and the
+  constexpr bool PAIR = sizeof(TM) == 2;  // 16-bit moments stored in pairs (32-bit words)
+  // non-temporal output stores possible: 4- or 8-byte stored words and the
   // interior-first lane map (32 output columns per row)
-  constexpr bool NTS = sizeof(TM) >= 4 && (BX - 2) % 32 == 0;
+  constexpr bool NTS = (sizeof(TM) >= 4 || PAIR) && (BX - 2) % 32 == 0;
   __shared__ FusedShared<BX, BY, PR, GC> sh;
 
   const int tid = threadIdx.x;
@@ -283,7 +298,8 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     const bool wall_tile = (wx && (item.x0 == 0 || item.x0 + BX - 2 >= nx)) ||
                            (wy && (item.y0 == 0 || item.y0 + BY - 2 >= ny));
 
-    // state views: phi [z][y][x]; moments [z][k][y][x] (plane-interleaved)
+    // state views: phi [z][y][x]; moments [z][k][y][x] (plane-interleaved;
+    // in 16-bit storage [z][k/2][y][x] of 32-bit pairs)
     const gptr<const TP> s_phi_g = (gptr<const TP>)(b.phi[parity]);
     const gptr<const TM> s_mom = (gptr<const TM>)(b.mom[parity]);
     const gptr<TP> d_phi_g = (gptr<TP>)(b.phi[1 - parity]);
@@ -291,6 +307,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     const uint32_t ucol = static_cast<uint32_t>(col);
     const uint32_t voff_p = ucol * static_cast<uint32_t>(sizeof(TP));  // byte offset in a phi plane
     const uint32_t voff_m = ucol * static_cast<uint32_t>(sizeof(TM));  // byte offset in a moment plane
+    const uint32_t voff_w = ucol * 4u;  // byte offset in a pair plane (16-bit storage)
     const int64_t plane_bp = plane * static_cast<int64_t>(sizeof(TP));
     const int64_t plane_bm = plane * static_cast<int64_t>(sizeof(TM));
 
@@ -368,13 +385,28 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     constexpr int NP = PX * PY;
     auto load_J = [&](int q, R (*v)[NPH]) {
       const gptr<const char> base = (gptr<const char>)s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * NM * plane_bm;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const gptr<const char> src = sbase(base + (1 + a) * plane_bm);
+      if constexpr (PAIR) {
+        // Jx: high half of pair 0 (P, Jx); Jy, Jz: pair 1.  Words are 4 bytes,
+        // like phi's elements, so phi's offsets address them.
+        const gptr<const char> src0 = sbase(base);
+        const gptr<const char> src1 = sbase(base + 2 * plane_bm);
 #pragma unroll
         for (int j = 0; j < NPH; ++j) {
-          const uint32_t off = phcol[j] / static_cast<uint32_t>(sizeof(TP)) * static_cast<uint32_t>(sizeof(TM));
-          v[a][j] = dec<R>(*(gptr<const TM>)(src + lane_off(off)), b.enc_off[1 + a], b.enc_inv[1 + a]);
+          const uint32_t w0 = *(gptr<const uint32_t>)(src0 + lane_off(phcol[j]));
+          const uint32_t w1 = *(gptr<const uint32_t>)(src1 + lane_off(phcol[j]));
+          v[0][j] = dec<R>(half_of<TM>(w0, 1), b.enc_off[1], b.enc_inv[1]);
+          v[1][j] = dec<R>(half_of<TM>(w1, 0), b.enc_off[2], b.enc_inv[2]);
+          v[2][j] = dec<R>(half_of<TM>(w1, 1), b.enc_off[3], b.enc_inv[3]);
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const gptr<const char> src = sbase(base + (1 + a) * plane_bm);
+#pragma unroll
+          for (int j = 0; j < NPH; ++j) {
+            const uint32_t off = phcol[j] / static_cast<uint32_t>(sizeof(TP)) * static_cast<uint32_t>(sizeof(TM));
+            v[a][j] = dec<R>(*(gptr<const TM>)(src + lane_off(off)), b.enc_off[1 + a], b.enc_inv[1 + a]);
+          }
         }
       }
     };
@@ -418,9 +450,18 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
     R nxt[NL];
     auto load_moments = [&](int q, R* m) {
       const gptr<const char> base = (gptr<const char>)s_mom + static_cast<int64_t>(map_plane(q, nz, wz)) * NM * plane_bm;
+      if constexpr (PAIR) {
 #pragma unroll
-      for (int k = 0; k < NL; ++k)
-        m[k] = dec<R>(*(gptr<const TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), b.enc_off[k], b.enc_inv[k]);
+        for (int w = 0; w < (NL + 1) / 2; ++w) {
+          const uint32_t v = *(gptr<const uint32_t>)(sbase(base + w * 2 * plane_bm) + lane_off(voff_w));
+          m[2 * w] = dec<R>(half_of<TM>(v, 0), b.enc_off[2 * w], b.enc_inv[2 * w]);
+          if (2 * w + 1 < NL) m[2 * w + 1] = dec<R>(half_of<TM>(v, 1), b.enc_off[2 * w + 1], b.enc_inv[2 * w + 1]);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+          m[k] = dec<R>(*(gptr<const TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), b.enc_off[k], b.enc_inv[k]);
+      }
     };
 
     // The two planes staged before the march and the first prefetch are all
@@ -497,9 +538,18 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         constexpr bool N = decltype(nt)::value;
         store_out<N>((gptr<TP>)(sbase((gptr<char>)d_phi_g + static_cast<int64_t>(Z) * plane_bp) + lane_off(voff_p)),
                      Enc<TP>::go(phin, 0.f, 1.f));
+        if constexpr (PAIR) {
 #pragma unroll
-        for (int k = 0; k < NM; ++k)
-          store_out<N>((gptr<TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)), Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]));
+          for (int w = 0; w < NM / 2; ++w)
+            store_out<N>((gptr<uint32_t>)(sbase(base + w * 2 * plane_bm) + lane_off(voff_w)),
+                         pack_pair<TM>(Enc<TM>::go(mv[2 * w], b.enc_off[2 * w], b.enc_scale[2 * w]),
+                                       Enc<TM>::go(mv[2 * w + 1], b.enc_off[2 * w + 1], b.enc_scale[2 * w + 1])));
+        } else {
+#pragma unroll
+          for (int k = 0; k < NM; ++k)
+            store_out<N>((gptr<TM>)(sbase(base + k * plane_bm) + lane_off(voff_m)),
+                         Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]));
+        }
       };
       if constexpr (NTS) {
         if (b.whole_rows) emit(std::true_type{});

@@ -43,17 +43,17 @@ def pack(state, prob, precision, nmom):
     tp, tm = _dtypes(precision)
     phi = np.zeros((nz, ny, pitch), dtype=tp)
     phi[:, :, :nx] = state[0].astype(tp)
-    if tm == "bf16":
-        mom = np.zeros((nz, nmom, ny, pitch), dtype=np.uint16)
-    else:
-        mom = np.zeros((nz, nmom, ny, pitch), dtype=tm)
+    if precision in ("fp16_os", "bf16_os"):
+        # pairs of fields (2p, 2p + 1) as one 32-bit word per node, the even
+        # field in the low half: [z][p][y][x][half]
+        mom = np.zeros((nz, nmom // 2, ny, pitch, 2), dtype=np.uint16 if tm == "bf16" else np.float16)
+        for k in range(nmom):
+            enc = state[1 + k].astype(np.float32) * np.float32(DEFAULT_SCALE[k])  # offset 0
+            mom[:, k // 2, :, :nx, k % 2] = _to_bf16(enc) if tm == "bf16" else enc.astype(np.float16)
+        return phi, mom
+    mom = np.zeros((nz, nmom, ny, pitch), dtype=tm)
     for k in range(nmom):
-        v = state[1 + k]
-        if precision in ("fp16_os", "bf16_os"):
-            enc = v.astype(np.float32) * np.float32(DEFAULT_SCALE[k])  # offset 0
-            mom[:, k, :, :nx] = _to_bf16(enc) if tm == "bf16" else enc.astype(np.float16)
-        else:
-            mom[:, k, :, :nx] = v.astype(tm)
+        mom[:, k, :, :nx] = state[1 + k].astype(tm)
     return phi, mom
 
 
@@ -62,7 +62,7 @@ def unpack(phi, mom, prob, precision, nmom):
     out = np.zeros((11, nz, ny, nx))
     out[0] = phi[:, :, :nx].astype(np.float64)
     for k in range(nmom):
-        m = mom[:, k, :, :nx]
+        m = mom[:, k // 2, :, :nx, k % 2] if precision in ("fp16_os", "bf16_os") else mom[:, k, :, :nx]
         if precision == "bf16_os":
             m = _from_bf16(m) * np.float32(1.0 / DEFAULT_SCALE[k])
         elif precision == "fp16_os":
