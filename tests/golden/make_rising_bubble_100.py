@@ -11,7 +11,7 @@ rho, u, p; and per field the maximum magnitude and the L2 norm over the whole
 box, which the parity test uses as the scale of its relative tolerance.
 
 Run from the repository root:  python tests/golden/make_rising_bubble_100.py
-(about 25 minutes on one core, ~8 GB of memory)."""
+(about 75 minutes on one core, ~8 GB of memory)."""
 import json
 import os
 import sys

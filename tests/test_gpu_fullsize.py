@@ -1,6 +1,7 @@
 """Parity at full workload sizes, in the launch configuration the benchmark
 times: one step of the GPU from the seeded initial state, checked at sampled
 nodes (walls, corners, interfaces, random) against the per-node oracle."""
+import os
 import sys
 
 import numpy as np
@@ -213,3 +214,44 @@ def test_eo_ga_sweep_fp32_one_step():
             got = ctx.state_at(i, pts)
             _log("Eo-Ga box %d (%s)" % (i, c.name))
             _compare(got, _reference(c, "fp32", pts), "fp32", force_scale(c.problem, c.phi, c.pstar, pts))
+
+
+GOLDEN_C2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "rising_bubble_128x128x256_100steps.json")
+
+
+def test_rising_bubble_128x128x256_100_steps_fp64():
+    """The full rising-bubble workload (128 x 128 x 256, walls on every face,
+    density ratio 1000, Eo 10, Mo 1e-3), 100 FP64 steps in the launch the
+    benchmark picks, against the FP64 oracle's run at 64 fixed nodes (walls,
+    corners, the bubble's poles and equator, random), stored by
+    tests/golden/make_rising_bubble_100.py: every state field and rho, u, p
+    within 1e-10 of the field's largest magnitude over the box."""
+    import json
+
+    with open(GOLDEN_C2) as fh:
+        gold = json.load(fh)
+    case = workloads.rising_bubble()
+    prob = case.problem
+    pts = [tuple(p) for p in gold["nodes"]]
+    _log("rising bubble 128x128x256: %d steps fp64 against the stored oracle run" % gold["steps"])
+    with lbm.Context(prob, "fp64") as ctx:
+        ctx.init_case(0, case)
+        ctx.autotune(2)
+        ctx.init_case(0, case)
+        _log("tuning %s" % ctx.tuning())
+        ctx.step(gold["steps"])
+        got = ctx.state_at(0, pts)
+        f = ctx.fields(0)
+    for k, name in enumerate(FIELDS):
+        ref = np.array(gold["state"][name])
+        err = np.abs(got[k] - ref).max() / gold["max_abs"][name]
+        _log("  %-4s max err / field scale %.3e" % (name, err))
+        assert err <= 1e-10, name
+    idx = tuple(np.array([[z for x, y, z in pts], [y for x, y, z in pts], [x for x, y, z in pts]]))
+    obs = {"rho": f["rho"][idx], "ux": f["u"][0][idx], "uy": f["u"][1][idx], "uz": f["u"][2][idx],
+           "p": f["p"][idx]}
+    for name, v in obs.items():
+        err = np.abs(v - np.array(gold["observables"][name])).max() / gold["max_abs"][name]
+        _log("  %-4s max err / field scale %.3e" % (name, err))
+        assert err <= 1e-10, name
