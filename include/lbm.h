@@ -69,7 +69,7 @@ typedef enum {
 
 typedef enum {
   LBM_FP64 = 0,    /* FP64 storage and arithmetic */
-  LBM_FP32 = 1,    /* FP32 storage and arithmetic; rho, nu, omega in FP64 */
+  LBM_FP32 = 1,    /* FP32 storage and arithmetic */
   LBM_FP16_OS = 2, /* phi FP32; 10 moments FP16 offset-and-scale; FP32 arithmetic */
   LBM_BF16_OS = 3  /* phi FP32; 10 moments BF16 offset-and-scale; FP32 arithmetic */
 } lbm_precision;
@@ -224,8 +224,9 @@ lbm_status lbm_get_state_points(lbm_ctx* ctx, int32_t box, int64_t n, const int6
 
 /* Offset-and-scale encoding of the 10 moments of one box in the 16-bit
  * storage modes: stored = (value - offset[k]) * scale[k], k over P, Jx, Jy, Jz,
- * Qxx, Qyy, Qzz, Qxy, Qxz, Qyz.  scale must be a positive power of two and
- * offset finite.  Without a call, offsets are 0 and scales 1024 (P), 4096
+ * Qxx, Qyy, Qzz, Qxy, Qxz, Qyz, computed in FP32 and rounded to nearest even.
+ * scale must be a power of two in [2^-126, 2^126] and offset finite in FP32.
+ * Without a call, offsets are 0 and scales 1024 (P), 4096
  * (J), 65536 (Q).  If the box already holds a state, that state is re-encoded
  * on the device (decoded with the previous offsets and scales, encoded with
  * the new ones), so its values change only by the rounding of the new

@@ -32,13 +32,9 @@ struct PBF16 { using TM = bf16_t;  using TP = float;  using R = float; };
 __device__ __forceinline__ float bf16_to_f32(bf16_t v) {
   return __uint_as_float(static_cast<uint32_t>(v) << 16);
 }
+// round to nearest even; NaN stays NaN (v_cvt_pk_bf16_f32 on gfx950)
 __device__ __forceinline__ bf16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) {  // Inf / NaN: keep class, quiet NaN
-    return static_cast<bf16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  }
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return static_cast<bf16_t>(u >> 16);
+  return __builtin_bit_cast(bf16_t, static_cast<__bf16>(f));
 }
 
 template <class R> __device__ __forceinline__ R dec(double v, float, float) { return static_cast<R>(v); }
@@ -50,6 +46,8 @@ template <class R> __device__ __forceinline__ R dec(bf16_t v, float off, float i
   return static_cast<R>(bf16_to_f32(v) * inv + off);
 }
 
+// Encoding of a stored value: identity for FP64 / FP32 storage; for the
+// 16-bit formats (v - off) * scale in FP32, rounded to nearest even.
 template <class T> struct Enc;
 template <> struct Enc<double> {
   template <class R> __device__ static double go(R v, float, float) { return static_cast<double>(v); }
@@ -106,6 +104,11 @@ __device__ __forceinline__ double rcp_newton(double d) {
   r = fma(r, e, r);
   e = fma(-d, r, 1.0);
   return fma(r, e, r);
+}
+// FP32: the hardware reciprocal (1 ulp) and one Newton step
+__device__ __forceinline__ float rcp_newton(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return fmaf(r, fmaf(-d, r, 1.0f), r);
 }
 __device__ __forceinline__ float inv_norm_eps(float s) {
   return __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(s) + 1e-12f);

@@ -15,7 +15,7 @@
 //       in x-y (per-axis stencils (1,4,1) and (-1,0,1)); with the filtered
 //       planes p-1, p, p+1 held in registers each thread gets the isotropic
 //       gradient and Laplacian of Sec. II.C at its node of plane p;
-//   (B) computes at that node rho, nu, omega (FP64), mu, the forces of Sec.
+//   (B) computes at that node rho, nu, omega, mu, the forces of Sec.
 //       II.C, the acceleration a = F/rho, u = J + a/2, the regularisation
 //       tensor a2 = Q + a a/4 (Eq. hermite_neq2 with the shifted equilibrium),
 //       the 17 monomial coefficients of the post-collision populations
@@ -227,10 +227,21 @@ template <class TM>
 __device__ __forceinline__ TM half_of(uint32_t w, int hi) {
   return __builtin_bit_cast(TM, static_cast<uint16_t>(hi ? (w >> 16) : w));
 }
+// Encodes moments v0 (low half) and v1 (high half) into one word: in FP16
+// each half is written in place by a mixed-precision multiply-add, in BF16
+// both are rounded by one packed conversion.
 template <class TM>
-__device__ __forceinline__ uint32_t pack_pair(TM lo, TM hi) {
-  return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, lo)) |
-         (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hi)) << 16);
+__device__ __forceinline__ uint32_t encode_pair(float v0, float v1, float o0, float s0, float o1, float s1) {
+  if constexpr (std::is_same_v<TM, _Float16>) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 h = {Enc<TM>::go(v0, o0, s0), Enc<TM>::go(v1, o1, s1)};
+    return __builtin_bit_cast(uint32_t, h);
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const f2 f = {(v0 - o0) * s0, (v1 - o1) * s1};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, b2));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -542,8 +553,8 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
 #pragma unroll
           for (int w = 0; w < NM / 2; ++w)
             store_out<N>((gptr<uint32_t>)(sbase(base + w * 2 * plane_bm) + lane_off(voff_w)),
-                         pack_pair<TM>(Enc<TM>::go(mv[2 * w], b.enc_off[2 * w], b.enc_scale[2 * w]),
-                                       Enc<TM>::go(mv[2 * w + 1], b.enc_off[2 * w + 1], b.enc_scale[2 * w + 1])));
+                         encode_pair<TM>(mv[2 * w], mv[2 * w + 1], b.enc_off[2 * w], b.enc_scale[2 * w],
+                                         b.enc_off[2 * w + 1], b.enc_scale[2 * w + 1]));
         } else {
 #pragma unroll
           for (int k = 0; k < NM; ++k)
@@ -604,19 +615,19 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
         Jz = cur[3 % NL];
       }
 
-      // density, viscosity and relaxation interpolation in FP64 (Sec. II.C),
+      // density, viscosity and relaxation interpolation (Sec. II.C),
       // evaluated at phi clamped to the model's range [0, 1]
-      const double phid = fmin(fmax(static_cast<double>(phi), 0.0), 1.0);
-      const double rho = b.rho_g + phid * b.drho;
-      const double nu = b.nu_g + phid * b.dnu;
-      const double tau = 3.0 * nu + 0.5;        // 1 / omega
-      const double r_rt = rcp_newton(rho * tau);  // one reciprocal for 1/rho and omega
-      const double inv_rho = tau * r_rt;
-      const double om_d = rho * r_rt;
-      const double bfac = 1.0 - b.rho_ref * inv_rho;  // body acceleration factor
-      const R om1 = static_cast<R>(1.0 - om_d);
-      const R irho = static_cast<R>(inv_rho);
-      const R cvis = static_cast<R>(-3.0 * nu * om_d * b.drho * inv_rho);
+      const R phid = fmin(fmax(phi, R(0)), R(1));
+      const R drho = static_cast<R>(b.drho);
+      const R rho = static_cast<R>(b.rho_g) + phid * drho;
+      const R nu = static_cast<R>(b.nu_g) + phid * static_cast<R>(b.dnu);
+      const R tau = R(3) * nu + R(0.5);  // 1 / omega
+      const R r_rt = rcp_newton(rho * tau);  // one reciprocal for 1/rho and omega
+      const R irho = tau * r_rt;
+      const R om_d = rho * r_rt;
+      const R bf = R(1) - static_cast<R>(b.rho_ref) * irho;  // body acceleration factor
+      const R om1 = R(1) - om_d;
+      const R cvis = R(-3) * nu * om_d * drho * irho;
 
       // The tensor the viscous correction contracts: the stored Q, or for the
       // gradient closure a2 itself, -(cs^2/omega)(d_a J_b + d_b J_a) with the
@@ -641,7 +652,7 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
           gJ[a][1] *= sdy;
           gJ[a][2] *= sg;
         }
-        const R ca = static_cast<R>(-tau * (1.0 / 3.0));  // -cs^2 / omega
+        const R ca = -tau * R(1.0 / 3.0);  // -cs^2 / omega
         Txx = ca * (gJ[0][0] + gJ[0][0]);
         Tyy = ca * (gJ[1][1] + gJ[1][1]);
         Tzz = ca * (gJ[2][2] + gJ[2][2]);
@@ -663,7 +674,6 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R qgx = Txx * gmx + Txy * gmy + Txz * gz;
       const R qgy = Txy * gmx + Tyy * gmy + Tyz * gz;
       const R qgz = Txz * gmx + Tyz * gmy + Tzz * gz;
-      const R bf = static_cast<R>(bfac);
       const R ax = csp * gmx + cvis * qgx + grx * bf;
       const R ay = csp * gmy + cvis * qgy + gry * bf;
       const R az = csp * gz + cvis * qgz + grz * bf;

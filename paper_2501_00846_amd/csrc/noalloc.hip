@@ -117,8 +117,8 @@ extern "C" lbm_status lbm_step_noalloc(const lbm_params* box, const lbm_tuning* 
   default_encoding(off, scale);
   if (enc_offset) {
     const int bad = check_encoding(enc_offset, enc_scale);
-    if (bad >= 10) return set_error(LBM_ERR_ARG, "%s: enc_offset[%d] must be finite", who, bad - 10);
-    if (bad >= 0) return set_error(LBM_ERR_ARG, "%s: enc_scale[%d] must be a positive power of two", who, bad);
+    if (bad >= 10) return set_error(LBM_ERR_ARG, "%s: enc_offset[%d] must be finite in FP32", who, bad - 10);
+    if (bad >= 0) return set_error(LBM_ERR_ARG, "%s: enc_scale[%d] must be a power of two in [2^-126, 2^126]", who, bad);
     std::copy(enc_offset, enc_offset + 10, off);
     std::copy(enc_scale, enc_scale + 10, scale);
   }

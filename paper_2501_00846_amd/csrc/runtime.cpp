@@ -343,10 +343,13 @@ void clear_error() { g_create_error.clear(); }
 
 int check_encoding(const double* offset, const double* scale) {
   for (int k = 0; k < 10; ++k) {
+    // scale = 2^(ex-1): a power of two that FP32 holds, with its reciprocal,
+    // as normal numbers, 2^-126 .. 2^126
     int ex = 0;
     const double m = std::frexp(scale[k], &ex);
-    if (!(std::isfinite(scale[k]) && scale[k] > 0 && m == 0.5)) return k;
-    if (!std::isfinite(offset[k])) return 10 + k;
+    if (!(std::isfinite(scale[k]) && scale[k] > 0 && m == 0.5 && ex >= -125 && ex <= 127)) return k;
+    // the kernels subtract the offset in FP32
+    if (!(std::isfinite(offset[k]) && std::isfinite(static_cast<float>(offset[k])))) return 10 + k;
   }
   return -1;
 }
@@ -670,8 +673,8 @@ lbm_status lbm_set_encoding(lbm_ctx* c, int32_t box, const double* offset, const
   if (s != LBM_OK) return s;
   if (!offset || !scale) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: NULL offset/scale");
   const int bad = lbm::check_encoding(offset, scale);
-  if (bad >= 10) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: offset[%d] must be finite", bad - 10);
-  if (bad >= 0) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: scale[%d] must be a positive power of two", bad);
+  if (bad >= 10) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: offset[%d] must be finite in FP32", bad - 10);
+  if (bad >= 0) return fail(c, LBM_ERR_ARG, "lbm_set_encoding: scale[%d] must be a power of two in [2^-126, 2^126]", bad);
   Box& b = c->boxes[box];
   if (c->precision != LBM_FP16_OS && c->precision != LBM_BF16_OS) return LBM_OK;
   const BoxDesc before = b.desc;

@@ -163,8 +163,8 @@ def sample_points(prob, rng, n_random=24, extra=()):
 def field_tolerance(precision, ref, offset=None, force=None):
     """Per-field absolute tolerance for one step from the same stored state.
 
-    FP64: 1e-12 of the field scale.  Reduced precision (FP32 arithmetic, FP64
-    only for rho, nu, omega): phi within 2e-5; every moment within 1e-5 of the
+    FP64: 1e-12 of the field scale.  Reduced precision (FP32 arithmetic):
+    phi within 2e-5; every moment within 1e-5 of the
     leading population scale max(|P|, |J|) -- each moment, Q included, is a
     signed sum of populations of that size, and the chemical potential is a
     near-cancelling difference whose FP32 rounding is amplified by 1/rho_g in

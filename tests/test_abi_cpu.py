@@ -150,6 +150,13 @@ def test_noalloc_step_checks_arguments_before_any_device_call():
     assert st == -1 and "power of two" in msg
     st, msg = _noalloc(_params(precision=2), off=[float("inf")] + [0.0] * 9, sc=[1024.0] * 10)
     assert st == -1 and "finite" in msg
+    # the scale and its reciprocal must be normal FP32 numbers, the offset finite in FP32
+    st, msg = _noalloc(_params(precision=2), off=[0.0] * 10, sc=[1024.0] * 9 + [2.0 ** 127])
+    assert st == -1 and "enc_scale[9]" in msg
+    st, msg = _noalloc(_params(precision=3), off=[0.0] * 10, sc=[2.0 ** -127] + [1024.0] * 9)
+    assert st == -1 and "enc_scale[0]" in msg
+    st, msg = _noalloc(_params(precision=2), off=[0.0, 1e39] + [0.0] * 8, sc=[1024.0] * 10)
+    assert st == -1 and "enc_offset[1]" in msg and "finite" in msg
     st, msg = _noalloc(_params(), tuning=lbm.lbm_tuning(33, 8, 4, 0))
     assert st == -2 and "unsupported" in msg
     st, msg = _noalloc(_params(), tuning=lbm.lbm_tuning(34, 8, 0, 0))
