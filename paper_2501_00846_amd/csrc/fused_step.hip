@@ -227,11 +227,15 @@ template <class TM>
 __device__ __forceinline__ TM half_of(uint32_t w, int hi) {
   return __builtin_bit_cast(TM, static_cast<uint16_t>(hi ? (w >> 16) : w));
 }
-// Encodes moments v0 (low half) and v1 (high half) into one word: in FP16
-// each half is written in place by a mixed-precision multiply-add, in BF16
-// both are rounded by one packed conversion.
-template <class TM>
+// Encodes moments v0 (low half) and v1 (high half) into one word; both are
+// rounded by one packed conversion (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32).
+// ZO: both offsets are +0, whose subtraction changes no value.
+template <class TM, bool ZO>
 __device__ __forceinline__ uint32_t encode_pair(float v0, float v1, float o0, float s0, float o1, float s1) {
+  if constexpr (ZO) {
+    o0 = 0.f;  // (v - (+0)) * s == v * s, bitwise (-0 - +0 = -0)
+    o1 = 0.f;
+  }
   if constexpr (std::is_same_v<TM, _Float16>) {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     const h2 h = {Enc<TM>::go(v0, o0, s0), Enc<TM>::go(v1, o1, s1)};
@@ -545,16 +549,19 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
       const R q_yz = a.yz - a.jy * a.jz;
       const R phin = phic + mob * lapc - advc - d * R(1.0 / 72.0);
       const R mv[10] = {P, a.jx, a.jy, a.jz, q_xx, q_yy, q_zz, q_xy, q_xz, q_yz};
-      auto emit = [&](auto nt) {
+      // ZO: every 16-bit offset is +0 (the default encoding), so the encode
+      // skips the subtraction of zeros (bitwise the same words)
+      auto emit = [&](auto nt, auto zo) {
         constexpr bool N = decltype(nt)::value;
+        constexpr bool ZO = decltype(zo)::value;
         store_out<N>((gptr<TP>)(sbase((gptr<char>)d_phi_g + static_cast<int64_t>(Z) * plane_bp) + lane_off(voff_p)),
                      Enc<TP>::go(phin, 0.f, 1.f));
         if constexpr (PAIR) {
 #pragma unroll
           for (int w = 0; w < NM / 2; ++w)
             store_out<N>((gptr<uint32_t>)(sbase(base + w * 2 * plane_bm) + lane_off(voff_w)),
-                         encode_pair<TM>(mv[2 * w], mv[2 * w + 1], b.enc_off[2 * w], b.enc_scale[2 * w],
-                                         b.enc_off[2 * w + 1], b.enc_scale[2 * w + 1]));
+                         encode_pair<TM, ZO>(mv[2 * w], mv[2 * w + 1], b.enc_off[2 * w], b.enc_scale[2 * w],
+                                             b.enc_off[2 * w + 1], b.enc_scale[2 * w + 1]));
         } else {
 #pragma unroll
           for (int k = 0; k < NM; ++k)
@@ -562,11 +569,19 @@ fused_step(const BoxDesc* __restrict__ boxes, const Item* __restrict__ items, in
                          Enc<TM>::go(mv[k], b.enc_off[k], b.enc_scale[k]));
         }
       };
+      auto emit_enc = [&](auto nt) {
+        if constexpr (PAIR) {
+          if (b.zero_offsets) emit(nt, std::true_type{});
+          else emit(nt, std::false_type{});
+        } else {
+          emit(nt, std::false_type{});
+        }
+      };
       if constexpr (NTS) {
-        if (b.whole_rows) emit(std::true_type{});
-        else emit(std::false_type{});
+        if (b.whole_rows) emit_enc(std::true_type{});
+        else emit_enc(std::false_type{});
       } else {
-        emit(std::false_type{});
+        emit_enc(std::false_type{});
       }
     };
 

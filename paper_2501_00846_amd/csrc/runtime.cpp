@@ -386,10 +386,12 @@ void fill_box_desc(const lbm_params& p, int precision, const double off[10], con
     rows = rows && reinterpret_cast<uintptr_t>(d.phi[s]) % 64 == 0 && reinterpret_cast<uintptr_t>(d.mom[s]) % 64 == 0;
   d.whole_rows = rows ? 1 : 0;
   const bool os = precision == LBM_FP16_OS || precision == LBM_BF16_OS;
+  d.zero_offsets = 1;
   for (int k = 0; k < 10; ++k) {
     d.enc_off[k] = os ? static_cast<float>(off[k]) : 0.f;
     d.enc_scale[k] = os ? static_cast<float>(scale[k]) : 1.f;
     d.enc_inv[k] = os ? static_cast<float>(1.0 / scale[k]) : 1.f;
+    if (d.enc_off[k] != 0.f || std::signbit(d.enc_off[k])) d.zero_offsets = 0;
   }
 }
 

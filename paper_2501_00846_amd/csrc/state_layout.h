@@ -36,6 +36,7 @@ struct BoxDesc {
   float enc_inv[10];      // 1 / scale (exact: powers of two)
   int32_t whole_rows;     // 1 if every stored row starts on a 64-byte boundary
                           // (buffer bases multiples of 64 bytes)
+  int32_t zero_offsets;   // 1 if every enc_off is +0 (the default encoding)
   int32_t pitch;          // elements from one stored row to the next (>= nx; the
                           // padding after column nx-1 is never read or written)
   double* aux;            // LBM_HIGH_ORDER_AC: 6 compact planes of nx*ny*nz doubles

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2501_00846_amd.workloads import PERIODIC, WALL, Problem
-from tests.gpu_util import (field_tolerance, gpu_run_state, oracle_run_state, quantize_state,
+from tests.gpu_util import (DEFAULT_SCALE, field_tolerance, gpu_run_state, oracle_run_state, quantize_state,
                             smooth_random_state, FIELDS)
 
 pytestmark = pytest.mark.gpu
@@ -103,3 +103,24 @@ def test_set_encoding_is_ignored_outside_16_bit_modes():
             before = ctx.get_state(0)
             ctx.set_encoding(0, ENC_OFFSET, ENC_SCALE)
             assert np.array_equal(ctx.get_state(0), before)
+
+
+@pytest.mark.parametrize("precision", ["fp16_os", "bf16_os"])
+def test_zero_offset_encode_equals_general_encode(precision):
+    """The step's encode skips the subtraction when every offset is +0 (the
+    default encoding).  Offsets of -0.0 take the general path, (v - (-0)) *
+    scale, which equals v * scale in value (only -0 turns into +0): five
+    steps of both boxes from the same state read back equal."""
+    from paper_2501_00846_amd import lbm
+
+    prob = Problem(33, 14, 11, bc=(W_, W_, W_), rho_l=1.0, rho_g=1e-3, nu_l=1 / 60, nu_g=1 / 6,
+                   sigma=0.01, gravity=(0.0, 0.0, -1e-5), rho_ref=1.0)
+    state = smooth_random_state(prob, seed=47)
+    got = []
+    for off in (np.zeros(10), np.full(10, -0.0)):
+        with lbm.Context(prob, precision) as ctx:
+            ctx.set_encoding(0, off, DEFAULT_SCALE)
+            ctx.set_state(0, state.reshape(-1))
+            ctx.step(5)
+            got.append(ctx.get_state(0))
+    assert np.array_equal(got[0], got[1])
