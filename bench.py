@@ -301,8 +301,8 @@ def cpu_baseline(config):
             case = WL.droplet_collision(n=n, radius=24.0 * n / 256)
         else:
             case = WL.drop_into_pool(n=n)
-        sample = "%s configuration scaled to %d^3, 2 steps" % (config, n)
-        nsteps = 2
+        nsteps = 4  # about 12 s of one core
+        sample = "%s configuration scaled to %d^3, %d steps" % (config, n, nsteps)
     from threadpoolctl import threadpool_limits
 
     st = S.initial_state(case.phi, case.u, case.pstar)
