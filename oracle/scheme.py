@@ -102,6 +102,41 @@ the paper gives no scheme):
       phi(-k) = phi(k - 1) for k = 1..4 (wall axes need at least 4 nodes),
       ghost velocity minus the mirrored one, ghost normal from the mirrored
       phi.  The flux divergence still telescopes, so sum phi is conserved.
+
+Finer phase-field grid (Problem.fine_phase; the finer grid for the phase field
+named as future work at the end of Sec. II.A, for which the paper gives no
+scheme):
+  F1  The phase field lives on a grid refined by 2 along every axis, cell
+      centred: coarse node i (the centre of the cell [i - 1/2, i + 1/2]) has
+      the two fine nodes 2i and 2i + 1 at i - 1/4 and i + 1/4.  The fine grid
+      has spacing h = 1/2 and 8 N nodes; periodic axes stay periodic (period
+      2n); a wall half-way beyond coarse node 0 is half-way beyond fine node
+      0 as well, so the fine ghosts mirror as in R11 (phi(-1) = phi(0), ...).
+  F2  The flow solver (phases 1-3) is unchanged and reads the coarse phi, the
+      restriction of the fine field: the mean of the 8 fine nodes of each
+      coarse cell.  This conserves the phase mass exactly
+      (sum phi_coarse = sum phi_fine / 8).
+  F3  The velocity of the phase-field update on the fine grid is the
+      trilinear interpolation of the coarse u = J + a/2 of the same step
+      (R13): along each axis fine node 2i takes 3/4 u(i) + 1/4 u(i - 1) and
+      2i + 1 takes 3/4 u(i) + 1/4 u(i + 1), with the coarse ghost velocity of
+      R11 (minus the mirrored one) beyond a wall.
+  F4  The fine update is the FTCS step of phase_update at spacing h with the
+      time step of the flow solver (1): the stencils of R6 divided by h (first
+      derivatives) and h^2 (Laplacian), M and W unchanged in lattice units, so
+      the interface keeps its width and spans twice as many fine nodes.
+      Stability of the diffusive part needs M / h^2 = 4 M below about 0.35
+      (the largest magnitude of the isotropic Laplacian's symbol is 5.78).
+  F5  Fine ghosts at walls follow R11 on the fine grid: phi mirrored, the
+      ghost flux phi u from the mirrored node with u negated, the ghost
+      normal from the mirrored phi.  The flux divergence telescopes, so the
+      fine phase mass is conserved.
+  F6  A coarse phi given at initialisation (or in a restart from the coarse
+      state) is carried to the fine grid with the interpolation of F3 (ghosts
+      mirrored, not negated), and the coarse phi becomes the restriction of
+      that fine field, so that the coarse phi is always the restriction of
+      the fine one.  Per axis the restriction of the interpolation is
+      g + (g(i-1) - 2 g(i) + g(i+1)) / 8.
 """
 from __future__ import annotations
 
@@ -511,6 +546,94 @@ def phase_update_high_order(st, u, prob):
     else:
         adv = divergence4(phi2 * up, 2)
     return st.phi - adv + M * laplacian4(phip, 4) - kac * divergence4(sharp, 2)
+
+
+# ----------------------------------------------------------------------------
+# Finer phase-field grid (F1-F6)
+# ----------------------------------------------------------------------------
+
+FINE_H = 0.5  # fine grid spacing in lattice units (F1)
+
+
+def prolong(g, prob, odd=False):
+    """Trilinear interpolation of a coarse (nz, ny, nx) field onto the fine
+    grid (2nz, 2ny, 2nx) of F1 (F3; ghosts beyond a wall mirrored, negated if
+    odd).  The axes are refined one after the other; each pass consumes that
+    axis's ghost layers."""
+    out = pad(g, prob, 1, odd=(odd, odd, odd))
+    for axis in range(3):  # array axes z, y, x of the padded field
+        n = out.shape[axis] - 2
+        lo, mid, hi = ([slice(None)] * 3 for _ in range(3))
+        lo[axis], mid[axis], hi[axis] = slice(0, n), slice(1, n + 1), slice(2, n + 2)
+        centre = out[tuple(mid)]
+        shape = list(centre.shape)
+        shape[axis] *= 2
+        fine = np.empty(shape)
+        even, oddn = [slice(None)] * 3, [slice(None)] * 3
+        even[axis], oddn[axis] = slice(0, None, 2), slice(1, None, 2)
+        fine[tuple(even)] = 0.75 * centre + 0.25 * out[tuple(lo)]  # fine node 2i at i - 1/4
+        fine[tuple(oddn)] = 0.75 * centre + 0.25 * out[tuple(hi)]  # fine node 2i + 1 at i + 1/4
+        out = fine
+    return out
+
+
+def restrict(phif):
+    """Mean of the 8 fine nodes of every coarse cell (F2)."""
+    nz, ny, nx = (s // 2 for s in phif.shape)
+    return phif.reshape(nz, 2, ny, 2, nx, 2).mean(axis=(1, 3, 5))
+
+
+def initial_fine_phase(phi, prob):
+    """Fine phase field from a coarse one, and the coarse phi the flow solver
+    then sees (F6)."""
+    phif = prolong(phi, prob)
+    return phif, restrict(phif)
+
+
+def phase_update_fine(phif, u, prob):
+    """FTCS step of the conservative Allen-Cahn equation on the fine grid
+    (F1, F3-F5):
+
+    phi_f' = phi_f - div_h(phi_f u_f) + M lap_h(phi_f) - kappa_AC div_h(phi_f (1 - phi_f) n_f),
+    div_h = div / h, lap_h = lap / h^2, n_f = grad_h(phi_f) / (|grad_h(phi_f)| + eps),
+    u_f the interpolation of the coarse u of this step.
+    """
+    h = FINE_H
+    M = prob.mobility
+    kac = 4.0 * M / prob.width
+    phip = pad(phif, prob, 2)
+    phi1 = shifted(phip, 2, (0, 0, 0), 1)               # fine phi on interior + 1 ghost layer
+    n1 = normal(grad(phip, 2, 1) / h)                    # ghost normal from mirrored phi
+    uf = np.stack([prolong(u[a], prob, odd=True) for a in range(3)])
+    up = np.stack([pad(uf[a], prob, 1, odd=(True, True, True)) for a in range(3)])
+    sharp = phi1 * (1.0 - phi1) * n1
+    adv = divergence(phi1 * up, 1) / h
+    lap = laplacian(phip, 2) / (h * h)
+    return phif - adv + M * lap - kac * divergence(sharp, 1) / h
+
+
+def step_fine(st, phif, prob):
+    """One time step with the phase field on the fine grid: phases 1-3 of
+    Sec. II.D on the coarse grid from st (whose phi is restrict(phif), F2),
+    then the fine phase update with that step's u (F3, F4), then the
+    restriction.  Returns the new coarse state and fine field."""
+    nf = node_fields(st, prob)
+    if prob.gradient_closure:
+        fpost, u, _, _ = collide_closed(st.P, st.J, nf["A"], nf["F"], nf["rho"], nf["omega"])
+    else:
+        fpost, u, _, _ = collide(st.P, st.J, st.Q, nf["F"], nf["rho"], nf["omega"])
+    f = stream_push(fpost, prob)
+    P, J, Q = moments(f)
+    if prob.gradient_closure:
+        Q = np.zeros_like(Q)  # G4
+    phif_new = phase_update_fine(phif, u, prob)
+    return State(restrict(phif_new), P, J, Q), phif_new
+
+
+def run_fine(st, phif, prob, nsteps):
+    for _ in range(nsteps):
+        st, phif = step_fine(st, phif, prob)
+    return st, phif
 
 
 def step(st, prob):

@@ -45,6 +45,7 @@ class Problem:
     literal_advection: bool = False  # u.grad(phi) instead of div(phi u)
     gradient_closure: bool = False   # a2 from the velocity gradient; state phi, P, J only
     high_order_ac: bool = False      # fourth-order stencils in the phase-field update
+    fine_phase: bool = False         # phase field on a grid refined by 2 per axis
 
     @property
     def shape(self):
