@@ -238,6 +238,9 @@ def run_mode(cases, precision, steps, warmup, tune, unbatched=False, tuning=None
     seg_ms = [ev[i].elapsed_time(ev[i + 1]) / (bounds[i + 1] - bounds[i]) for i in range(nseg)]
     nodes = ctx.total_nodes
     bpl = ctx.bytes_per_update
+    if getattr(cases[0].problem, "fine_phase", False):
+        # the fine phase field is state too: 8 fine nodes read and written per update
+        bpl += 16 * (8 if precision == "fp64" else 4)
     diag = ctx.diagnostics(0)
     # cost of the FP64 reductions of every box (one launch, synchronised):
     # best of three calls
@@ -534,6 +537,8 @@ def main():
                          "velocity gradient (5-field state)")
     ap.add_argument("--high-order", action="store_true",
                     help="fourth-order phase-field update (the flow solver keeps its stencils)")
+    ap.add_argument("--fine-phase", action="store_true",
+                    help="phase field on a grid refined by 2 per axis (the flow solver reads its restriction)")
     ap.add_argument("--tuning", default=None, metavar="BX,BY,ZCHUNK,PERSISTENT",
                     help="fixed launch configuration instead of autotuning")
     args = ap.parse_args()
@@ -573,7 +578,14 @@ def main():
         for c in cases:
             c.problem.high_order_ac = True
         desc += ", fourth-order phase-field update"
-    cfg_key = args.config + ("/gc" if gc else "") + ("/ho" if args.high_order else "")
+    if args.fine_phase:
+        if args.high_order:
+            raise SystemExit("--fine-phase and --high-order are separate variants")
+        for c in cases:
+            c.problem.fine_phase = True
+        desc += ", phase field on the grid refined by 2"
+    cfg_key = args.config + ("/gc" if gc else "") + ("/ho" if args.high_order else "") + \
+        ("/fine" if args.fine_phase else "")
     problems = [c.problem for c in cases]
     # per-field error against the FP64 run: only for single-box workloads
     # that run FP64 among their modes
@@ -633,7 +645,8 @@ def main():
     roof.update({"traffic": traffic, "copy_gbs": round(copy_gbs, 1),
                  "frac_of_copy": round(m["achieved_gbs"] / copy_gbs, 4),
                  "hbm_floor_ms": round(hbm_floor_ms, 4), "alu": alu,
-                 "kernel": "fused_step (%s)" % head + (" + ho_flux + ho_phase" if args.high_order else ""),
+                 "kernel": "fused_step (%s)" % head + (" + ho_flux + ho_phase" if args.high_order else "") +
+                           (" + ho_flux (u) + fine_flux + fine_phase + fine_restrict" if args.fine_phase else ""),
                  "kernel_ms": round(m["kernel_ms"], 4),
                  "bytes_per_update": m["bytes_per_update"], "nodes_per_launch": m["nodes"]})
     cpu = None
@@ -655,7 +668,9 @@ def main():
         "dtype": DTYPE[head],
         "data": "synthetic (seeded initial droplet/bubble fields)",
         "config": {"workload": desc, "config": args.config, "closure": args.closure,
-                   "phase_update": "fourth-order" if args.high_order else "second-order", "nodes": m["nodes"],
+                   "phase_update": ("fourth-order" if args.high_order else
+                                    "second-order on the grid refined by 2" if args.fine_phase else "second-order"),
+                   "nodes": m["nodes"],
                    "precision": head, "tuning": m["tuning"], "steps_per_launch": 1},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -95,7 +95,24 @@ enum {
    * device memory (velocity and sharpening flux of level n) and runs two
    * more kernels.  All boxes of a context must agree on this flag and, with
    * it, on LBM_LITERAL_ADVECTION; not available through lbm_step_noalloc. */
-  LBM_HIGH_ORDER_AC = 4
+  LBM_HIGH_ORDER_AC = 4,
+  /* Finer phase-field grid (the finer grid named as future work at the end
+   * of Sec. II.A): phi lives on a grid refined by 2 per axis, cell centred
+   * (fine nodes 2i and 2i + 1 at i - 1/4 and i + 1/4 of coarse node i,
+   * spacing 1/2), and is advanced by the FTCS update of Sec. II.D with the
+   * stencils of Sec. II.C at that spacing and the trilinear interpolation of
+   * the coarse velocity; the flow solver reads the coarse phi, the mean of
+   * the 8 fine nodes of each cell.  A phi given to lbm_init_phase or
+   * lbm_set_state is carried to the fine grid by the same interpolation and
+   * the coarse phi becomes its restriction; lbm_get_fine_phase /
+   * lbm_set_fine_phase read and write the fine field itself.  The diffusive
+   * part is stable for 4 * mobility below about 0.35.  Each box keeps two
+   * fine phi buffers (8 N values of the phi storage type each), the flux of a
+   * step (3 (2nx+2)(2ny+2)(2nz+2) doubles) and the coarse velocity (3 N
+   * doubles); a step runs four more kernels.  All boxes of a context must
+   * agree on this flag; not combined with LBM_HIGH_ORDER_AC or
+   * LBM_LITERAL_ADVECTION, and not available through lbm_step_noalloc. */
+  LBM_FINE_PHASE = 8
 };
 
 /* One box.  phi = 1 is the liquid (subscript l), phi = 0 the gas (g). */
@@ -105,7 +122,8 @@ typedef struct {
   int32_t lattice;        /* lbm_lattice */
   int32_t bc[3];          /* lbm_bc per axis x, y, z */
   int32_t precision;      /* lbm_precision; identical for all boxes of a context */
-  int32_t flags;          /* LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE | LBM_HIGH_ORDER_AC, or 0 */
+  int32_t flags;          /* LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE | LBM_HIGH_ORDER_AC |
+                             LBM_FINE_PHASE, or 0 */
   double rho_l, rho_g;    /* phase densities, > 0 (Sec. II.C) */
   double nu_l, nu_g;      /* kinematic viscosities, > 0; omega = 1/(3 nu + 1/2) */
   double sigma;           /* surface tension, >= 0 (Sec. II.C: beta = 12 sigma/W, kappa = 3 sigma W/2) */
@@ -221,6 +239,16 @@ lbm_status lbm_set_state(lbm_ctx* ctx, int32_t box, const double* state);
  * boxes without copying the whole state.  Synchronises. */
 lbm_status lbm_get_state_points(lbm_ctx* ctx, int32_t box, int64_t n, const int64_t* node,
                                 double* out);
+
+/* The fine phase field of a box created with LBM_FINE_PHASE: 8 N doubles,
+ * index X + 2nx (Y + 2ny Z) over the fine grid (2nx x 2ny x 2nz, node X at
+ * X/2 - 1/4 in lattice units).  get synchronises and reports
+ * LBM_ERR_UNSTABLE for non-finite values; set replaces the fine field of a
+ * box that holds a state (LBM_ERR_STATE otherwise) and sets the coarse phi
+ * to its restriction (an exact restart together with lbm_set_state of the
+ * other fields first).  LBM_ERR_UNSUPPORTED for a box without the flag. */
+lbm_status lbm_get_fine_phase(lbm_ctx* ctx, int32_t box, double* out);
+lbm_status lbm_set_fine_phase(lbm_ctx* ctx, int32_t box, const double* in);
 
 /* Offset-and-scale encoding of the 10 moments of one box in the 16-bit
  * storage modes: stored = (value - offset[k]) * scale[k], k over P, Jx, Jy, Jz,

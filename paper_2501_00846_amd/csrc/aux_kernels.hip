@@ -5,6 +5,7 @@
 // except the fourth-order kernels, and those only with LBM_HIGH_ORDER_AC.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -477,12 +478,13 @@ __global__ void __launch_bounds__(kDiagThreads) diag_final_kernel(const double* 
 
 constexpr int kHoZ = 64;  // planes per work unit / tile of the z-marches
 
-// u and S = phi (1 - phi) n4 per node into b.aux (6 compact planes).  Work
-// units: one column (x, y) over up to kHoZ planes, consecutive threads on
-// consecutive x.  Per plane the thread filters phi over its 3 x 3 columns at
-// spacing 1 (F1) and at spacing 2 (F2), the raw values of the next planes
-// and the node's moments loaded one plane ahead.
-template <class PR, bool GC>
+// u and S = phi (1 - phi) n4 per node into b.aux (6 compact planes; with
+// WS false u only, 3 planes, for the finer phase grid).  Work units: one
+// column (x, y) over up to kHoZ planes, consecutive threads on consecutive x.
+// Per plane the thread filters phi over its 3 x 3 columns at spacing 1 (F1)
+// and at spacing 2 (F2), the raw values of the next planes and the node's
+// moments loaded one plane ahead.
+template <class PR, bool GC, bool WS>
 __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
   using TM = typename PR::TM;
   using TP = typename PR::TP;
@@ -539,26 +541,28 @@ __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict_
       }
     };
     // F1 of planes z-1, z, z+1; F2 of planes z-2 .. z+2
-    double F1[3][4], F2[5][4];
+    double F1[3][4], F2[5][4] = {};
     double JFm[GC ? 3 : 1][4], JF0[GC ? 3 : 1][4], JFn[GC ? 3 : 1][4];
     issue1(z0 - 1);
     filt(r1, F1[0]);
     issue1(z0);
     filt(r1, F1[1]);
-    for (int k = 0; k < 4; ++k) {
-      issue2(z0 - 2 + k);
-      filt(r2, F2[k]);
+    if constexpr (WS) {
+      for (int k = 0; k < 4; ++k) {
+        issue2(z0 - 2 + k);
+        filt(r2, F2[k]);
+      }
     }
     if constexpr (GC) {
       filter_J(z0 - 1, JFm);
       filter_J(z0, JF0);
     }
     issue1(z0 + 1);
-    issue2(z0 + 2);
+    if constexpr (WS) issue2(z0 + 2);
     issue_mom(z0);
     for (int z = z0; z < z1; ++z) {
       filt(r1, F1[2]);  // plane z + 1
-      filt(r2, F2[4]);  // plane z + 2
+      if constexpr (WS) filt(r2, F2[4]);  // plane z + 2
       if constexpr (GC) filter_J(z + 1, JFn);
       double m[10];
 #pragma unroll
@@ -567,7 +571,7 @@ __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict_
       for (int k = 0; k < NMOM; ++k) m[k] = dec<double>(rm[k], b.enc_off[k], b.enc_inv[k]);
       if (z + 1 < z1) {
         issue1(z + 2);
-        issue2(z + 3);
+        if constexpr (WS) issue2(z + 3);
         issue_mom(z + 1);
       }
       const double phi = F1[1][3];
@@ -606,12 +610,13 @@ __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict_
         const double F = mu * g[a] - P * (1.0 / 3.0) * b.drho * g[a] - 3.0 * nu * om * qg +
                          (rho - b.rho_ref) * b.grav[a];
         aux[a * n + i] = m[1 + a] + 0.5 * F / rho;
-        aux[(3 + a) * n + i] = pp * g4[a] * inv;
+        if constexpr (WS) aux[(3 + a) * n + i] = pp * g4[a] * inv;
       }
       for (int k = 0; k < 4; ++k) {
         F1[0][k] = F1[1][k];
         F1[1][k] = F1[2][k];
-        for (int p = 0; p < 4; ++p) F2[p][k] = F2[p + 1][k];
+        if constexpr (WS)
+          for (int p = 0; p < 4; ++p) F2[p][k] = F2[p + 1][k];
       }
       if constexpr (GC)
         for (int a = 0; a < 3; ++a)
@@ -764,6 +769,280 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
   }
 }
 
+// ---------------------------------------------------------------------------
+// Finer phase-field grid (LBM_FINE_PHASE)
+// ---------------------------------------------------------------------------
+// The finer grid that Sec. II.A names as future work, with no scheme given
+// there.  The phase field lives on a grid refined by 2 per axis, cell
+// centred: coarse node i has the fine nodes 2i and 2i + 1 at i - 1/4 and
+// i + 1/4, spacing h = 1/2.  The flow solver (the fused step, unchanged)
+// reads the coarse phi, which is kept equal to the mean of the 8 fine nodes
+// of its cell.  After the fused step of a step, reading level n:
+//   ho_flux_kernel<PR, GC, false>  coarse u = J + a/2 into b.aux;
+//   fine_flux_kernel   G = phi u_f + (4M/W) phi (1 - phi) n over the fine grid
+//                      grown by one ghost layer (b.fgrid), u_f the trilinear
+//                      interpolation of the coarse u, n from the isotropic
+//                      gradient at spacing h;
+//   fine_phase_kernel  phi_f' = phi_f - div_h G + M lap_h phi_f into the other
+//                      fine buffer (the isotropic stencils of Sec. II.C
+//                      divided by h and h^2);
+//   fine_restrict_kernel  coarse phi' = mean of the 8 fine nodes, over the
+//                      fused step's phi output.
+// A ghost node of the fine grid beyond a wall takes the flux of its mirror
+// node with u negated per crossed wall and the crossed components of the
+// normal negated (the normal of the mirrored phi); the divergence then
+// telescopes, and the fine phase mass is conserved.
+
+__device__ __forceinline__ int64_t fine_at(const BoxDesc& b, int x, int y, int z) {
+  return (static_cast<int64_t>(z) * (2 * b.ny) + y) * (2 * b.nx) + x;
+}
+// component a of the flux at padded fine coordinates (0 and 2n + 1: ghosts)
+__device__ __forceinline__ int64_t fgrid_at(const BoxDesc& b, int a, int xp, int yp, int zp) {
+  const int64_t px = 2 * b.nx + 2, py = 2 * b.ny + 2, pz = 2 * b.nz + 2;
+  return ((a * pz + zp) * py + yp) * px + xp;
+}
+
+// Trilinear interpolation at fine node (X, Y, Z) of a coarse field read by
+// ld(x, y, z) at mapped coordinates: per axis coarse node X >> 1 with weight
+// 3/4 and its neighbour towards the fine node (X even: below, odd: above)
+// with weight 1/4.  ODD: a coarse ghost beyond a wall is minus the mirrored
+// value (velocity); otherwise the mirrored value.
+template <bool ODD, class Load>
+__device__ __forceinline__ double interp_fine(const BoxDesc& b, int X, int Y, int Z, const Load& ld) {
+  int cx[2], cy[2], cz[2], kx[2] = {0, 0}, ky[2] = {0, 0}, kz[2] = {0, 0};
+  cx[0] = X >> 1;
+  cy[0] = Y >> 1;
+  cz[0] = Z >> 1;
+  cx[1] = map_axis(cx[0] + ((X & 1) ? 1 : -1), b.nx, b.wall[0], kx[1]);
+  cy[1] = map_axis(cy[0] + ((Y & 1) ? 1 : -1), b.ny, b.wall[1], ky[1]);
+  cz[1] = map_axis(cz[0] + ((Z & 1) ? 1 : -1), b.nz, b.wall[2], kz[1]);
+  double s = 0.0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const double w = (dx ? 0.25 : 0.75) * (dy ? 0.25 : 0.75) * (dz ? 0.25 : 0.75);
+        double v = ld(cx[dx], cy[dy], cz[dz]);
+        if (ODD && ((kx[dx] + ky[dy] + kz[dz]) & 1)) v = -v;
+        s += w * v;
+      }
+  return s;
+}
+
+// fine phi of buffer s from the coarse phi of buffer s (initialisation)
+template <class PR>
+__global__ void fine_prolong_kernel(BoxDesc b, int s) {
+  using TP = typename PR::TP;
+  const int fx = 2 * b.nx, fy = 2 * b.ny;
+  const int64_t nf = static_cast<int64_t>(fx) * fy * (2 * b.nz);
+  const gptr<const TP> cphi = (gptr<const TP>)b.phi[s];
+  const gptr<TP> fphi = (gptr<TP>)b.fphi[s];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nf;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int X = static_cast<int>(i % fx), Y = static_cast<int>((i / fx) % fy), Z = static_cast<int>(i / fx / fy);
+    auto ld = [&](int x, int y, int z) { return dec<double>(cphi[phi_at(b, x, y, z)], 0.f, 1.f); };
+    fphi[i] = Enc<TP>::go(interp_fine<false>(b, X, Y, Z, ld), 0.f, 1.f);
+  }
+}
+
+// coarse phi of buffer s = mean of the 8 fine nodes of each cell (fine buffer s)
+template <class PR>
+__global__ void __launch_bounds__(256) fine_restrict_kernel(const BoxDesc* __restrict__ boxes, int box0, int s) {
+  using TP = typename PR::TP;
+  const BoxDesc& b = boxes[box0 + blockIdx.y];
+  const int64_t n = static_cast<int64_t>(b.nx) * b.ny * b.nz;
+  const gptr<const TP> fphi = (gptr<const TP>)b.fphi[s];
+  const gptr<TP> cphi = (gptr<TP>)b.phi[s];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int x, y, z;
+    node_xyz(b, i, x, y, z);
+    double sum = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) sum += dec<double>(fphi[fine_at(b, 2 * x + dx, 2 * y + dy, 2 * z + dz)], 0.f, 1.f);
+    cphi[phi_at(b, x, y, z)] = Enc<TP>::go(0.125 * sum, 0.f, 1.f);
+  }
+}
+
+template <class PR>
+__global__ void fine_encode_kernel(BoxDesc b, int s, const double* __restrict__ src, int64_t n) {
+  using TP = typename PR::TP;
+  const gptr<TP> fphi = (gptr<TP>)b.fphi[s];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    fphi[i] = Enc<TP>::go(src[i], 0.f, 1.f);
+}
+
+template <class PR>
+__global__ void fine_decode_kernel(BoxDesc b, int s, double* __restrict__ dst, int64_t n) {
+  using TP = typename PR::TP;
+  const gptr<const TP> fphi = (gptr<const TP>)b.fphi[s];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = dec<double>(fphi[i], 0.f, 1.f);
+}
+
+// Work units of fine_flux_kernel per box: one padded column over a chunk of
+// up to kHoZ fine planes, plus the two ghost planes of every column.
+__host__ __device__ inline int64_t fine_flux_units(int nx, int ny, int nz) {
+  return static_cast<int64_t>(2 * nx + 2) * (2 * ny + 2) * ((2 * nz + kHoZ - 1) / kHoZ + 2);
+}
+__host__ __device__ inline int64_t fine_phase_units(int nx, int ny, int nz) {
+  return static_cast<int64_t>(2 * nx) * (2 * ny) * ((2 * nz + kHoZ - 1) / kHoZ);
+}
+
+// The flux G at every node of the padded fine grid.  A unit marches its
+// source column (the mirror or periodic image of a ghost column) over its
+// planes with the x-y filtered phi planes z-1, z, z+1 in registers; a ghost
+// plane is a unit of one plane at its source plane.
+template <class PR>
+__global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
+  using TP = typename PR::TP;
+  const BoxDesc& b = boxes[box0 + blockIdx.y];
+  const int nx = b.nx, ny = b.ny;
+  const int fx = 2 * nx, fy = 2 * ny, fz = 2 * b.nz;
+  const int px = fx + 2, py = fy + 2;
+  const int64_t ncolp = static_cast<int64_t>(px) * py;
+  const int nch = (fz + kHoZ - 1) / kHoZ;
+  const int64_t units = ncolp * (nch + 2);
+  const int64_t n = static_cast<int64_t>(nx) * ny * b.nz;
+  const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
+  const double* __restrict__ u = b.aux;
+  double* __restrict__ G = b.fgrid;
+  const double kac = b.kappa_ac;
+  constexpr double kInvH = 2.0;  // 1 / h
+  for (int64_t un = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; un < units;
+       un += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t col = un % ncolp;
+    const int ch = static_cast<int>(un / ncolp);
+    const int Xp = static_cast<int>(col % px), Yp = static_cast<int>(col / px);
+    int kxs, kys, kzs = 0;
+    const int xm = map_axis(Xp - 1, fx, b.wall[0], kxs);
+    const int ym = map_axis(Yp - 1, fy, b.wall[1], kys);
+    int zs, ze, zd;
+    if (ch < nch) {
+      zs = ch * kHoZ;
+      ze = min(zs + kHoZ, fz);
+      zd = zs + 1;
+    } else if (ch == nch) {
+      zs = map_axis(-1, fz, b.wall[2], kzs);
+      ze = zs + 1;
+      zd = 0;
+    } else {
+      zs = map_axis(fz, fz, b.wall[2], kzs);
+      ze = zs + 1;
+      zd = fz + 1;
+    }
+    int xs[3], ys[3];
+    for (int c = -1; c <= 1; ++c) {
+      xs[c + 1] = map_axis(xm + c, fx, b.wall[0]);
+      ys[c + 1] = map_axis(ym + c, fy, b.wall[1]);
+    }
+    TP r[9];
+    auto issue = [&](int q) {
+      const int zq = map_axis(q, fz, b.wall[2]);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) r[k] = fphi[fine_at(b, xs[k % 3], ys[k / 3], zq)];
+    };
+    auto filt = [&](double F[4]) {
+      auto ld = [&](int, int, int cx, int cy) { return dec<double>(r[cy * 3 + cx], 0.f, 1.f); };
+      diag_filter(ld, xs, ys, F);
+    };
+    // signs of the destination (ghost) node: u negated per crossed wall, the
+    // crossed components of the normal negated
+    const double su = ((kxs + kys + kzs) & 1) ? -1.0 : 1.0;
+    const double tn[3] = {kxs ? -1.0 : 1.0, kys ? -1.0 : 1.0, kzs ? -1.0 : 1.0};
+    double F[3][4];
+    issue(zs - 1);
+    filt(F[0]);
+    issue(zs);
+    filt(F[1]);
+    issue(zs + 1);
+    for (int z = zs; z < ze; ++z) {
+      filt(F[2]);  // plane z + 1
+      if (z + 1 < ze) issue(z + 2);
+      const double phi = F[1][3];
+      const double g[3] = {(F[0][1] + 4.0 * F[1][1] + F[2][1]) * (kInvH / 72.0),
+                           (F[0][2] + 4.0 * F[1][2] + F[2][2]) * (kInvH / 72.0), (F[2][0] - F[0][0]) * (kInvH / 72.0)};
+      const double inv = 1.0 / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + 1e-12);
+      const double pp = phi * (1.0 - phi);
+      for (int a = 0; a < 3; ++a) {
+        auto ldu = [&](int x, int y, int zc) { return u[a * n + (static_cast<int64_t>(zc) * ny + y) * nx + x]; };
+        const double uf = interp_fine<true>(b, xm, ym, z, ldu);
+        G[fgrid_at(b, a, Xp, Yp, zd + (z - zs))] = su * phi * uf + kac * (tn[a] * pp * g[a] * inv);
+      }
+      for (int k = 0; k < 4; ++k) {
+        F[0][k] = F[1][k];
+        F[1][k] = F[2][k];
+      }
+    }
+  }
+}
+
+// phi_f' = phi_f - div_h G + M lap_h phi_f.  A unit marches one fine column
+// over up to kHoZ planes with the filtered planes z-1, z, z+1 of phi and of G
+// (read from the padded grid, no ghost logic) in registers.
+template <class PR>
+__global__ void __launch_bounds__(256) fine_phase_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
+  using TP = typename PR::TP;
+  const BoxDesc& b = boxes[box0 + blockIdx.y];
+  const int fx = 2 * b.nx, fy = 2 * b.ny, fz = 2 * b.nz;
+  const int64_t ncol = static_cast<int64_t>(fx) * fy;
+  const int64_t units = ncol * ((fz + kHoZ - 1) / kHoZ);
+  const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
+  const gptr<TP> fout = (gptr<TP>)b.fphi[1 - parity];
+  const double* __restrict__ G = b.fgrid;
+  const double mob = b.mobility;
+  constexpr double kInvH = 2.0, kInvH2 = 4.0;
+  for (int64_t un = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; un < units;
+       un += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t col = un % ncol;
+    const int X = static_cast<int>(col % fx), Y = static_cast<int>(col / fx);
+    const int z0 = static_cast<int>(un / ncol) * kHoZ, z1 = min(z0 + kHoZ, fz);
+    int xs[3], ys[3];
+    for (int c = -1; c <= 1; ++c) {
+      xs[c + 1] = map_axis(X + c, fx, b.wall[0]);
+      ys[c + 1] = map_axis(Y + c, fy, b.wall[1]);
+    }
+    // filtered values of plane q: v[0] = sum w cx Gx, v[1] = sum w cy Gy,
+    // v[2] = sum w Gz, v[3] = sum w phi (w = (1, 4, 1) x (1, 4, 1)), v[4] = phi
+    auto plane = [&](int q, double v[5]) {
+      const int zq = map_axis(q, fz, b.wall[2]);
+      double hx = 0, hy = 0, hz = 0, L = 0;
+      for (int cy = -1; cy <= 1; ++cy)
+        for (int cx = -1; cx <= 1; ++cx) {
+          const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0);
+          const double ph = dec<double>(fphi[fine_at(b, xs[cx + 1], ys[cy + 1], zq)], 0.f, 1.f);
+          L += w * ph;
+          if (cx == 0 && cy == 0) v[4] = ph;
+          const int xp = X + 1 + cx, yp = Y + 1 + cy, zp = q + 1;
+          if (cx) hx += w * cx * G[fgrid_at(b, 0, xp, yp, zp)];
+          if (cy) hy += w * cy * G[fgrid_at(b, 1, xp, yp, zp)];
+          hz += w * G[fgrid_at(b, 2, xp, yp, zp)];
+        }
+      v[0] = hx;
+      v[1] = hy;
+      v[2] = hz;
+      v[3] = L;
+    };
+    double V[3][5];
+    plane(z0 - 1, V[0]);
+    plane(z0, V[1]);
+    for (int z = z0; z < z1; ++z) {
+      plane(z + 1, V[2]);
+      const double phi = V[1][4];
+      const double div = ((V[0][0] + 4.0 * V[1][0] + V[2][0]) + (V[0][1] + 4.0 * V[1][1] + V[2][1]) +
+                          (V[2][2] - V[0][2])) * (kInvH / 72.0);
+      const double lap = ((V[0][3] + 4.0 * V[1][3] + V[2][3]) * (1.0 / 36.0) - 6.0 * phi) * kInvH2;
+      fout[fine_at(b, X, Y, z)] = Enc<TP>::go(phi - div + mob * lap, 0.f, 1.f);
+      for (int k = 0; k < 5; ++k) {
+        V[0][k] = V[1][k];
+        V[1][k] = V[2][k];
+      }
+    }
+  }
+}
+
 int grid_for(int64_t n, int threads) {
   int64_t g = (n + threads - 1) / threads;
   if (g > 65536) g = 65536;
@@ -829,9 +1108,9 @@ hipError_t launch_high_order_phase(int precision, bool gc, bool literal, const B
   return dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
     if (gc)
-      hipLaunchKernelGGL((ho_flux_kernel<PR, true>), dim3(flux_blocks, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+      hipLaunchKernelGGL((ho_flux_kernel<PR, true, true>), dim3(flux_blocks, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
     else
-      hipLaunchKernelGGL((ho_flux_kernel<PR, false>), dim3(flux_blocks, nbox), dim3(256), 0, stream, d_boxes, box0,
+      hipLaunchKernelGGL((ho_flux_kernel<PR, false, true>), dim3(flux_blocks, nbox), dim3(256), 0, stream, d_boxes, box0,
                          parity);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -841,6 +1120,74 @@ hipError_t launch_high_order_phase(int precision, bool gc, bool literal, const B
     else
       hipLaunchKernelGGL((ho_phase_kernel<PR, false>), dim3(phase_tiles, nbox), dim3(256), 0, stream, d_boxes, box0,
                          parity);
+    return hipGetLastError();
+  });
+}
+
+int fine_blocks_per_box(int64_t max_units) {
+  const int64_t nb = (max_units + 255) / 256;
+  return static_cast<int>(nb < 1 ? 1 : (nb > 8192 ? 8192 : nb));
+}
+
+int64_t fine_units(int nx, int ny, int nz) {
+  return std::max(fine_flux_units(nx, ny, nz), fine_phase_units(nx, ny, nz));
+}
+
+hipError_t launch_fine_init(int precision, const BoxDesc& box, const BoxDesc* d_box, int parity, hipStream_t stream) {
+  const int64_t nf = 8 * static_cast<int64_t>(box.nx) * box.ny * box.nz;
+  const int64_t n = nf / 8;
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((fine_prolong_kernel<PR>), dim3(grid_for(nf, 256)), dim3(256), 0, stream, box, parity);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fine_restrict_kernel<PR>), dim3(grid_for(n, 256), 1), dim3(256), 0, stream, d_box, 0, parity);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_fine_set(int precision, const BoxDesc& box, const BoxDesc* d_box, int parity, const double* d_src,
+                           hipStream_t stream) {
+  const int64_t nf = 8 * static_cast<int64_t>(box.nx) * box.ny * box.nz;
+  const int64_t n = nf / 8;
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((fine_encode_kernel<PR>), dim3(grid_for(nf, 256)), dim3(256), 0, stream, box, parity, d_src, nf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fine_restrict_kernel<PR>), dim3(grid_for(n, 256), 1), dim3(256), 0, stream, d_box, 0, parity);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_fine_get(int precision, const BoxDesc& box, int parity, double* d_dst, hipStream_t stream) {
+  const int64_t nf = 8 * static_cast<int64_t>(box.nx) * box.ny * box.nz;
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((fine_decode_kernel<PR>), dim3(grid_for(nf, 256)), dim3(256), 0, stream, box, parity, d_dst, nf);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_fine_phase(int precision, bool gc, const BoxDesc* d_boxes, int box0, int nbox, int parity,
+                             int u_blocks, int fine_blocks, int restrict_blocks, hipStream_t stream) {
+  if (nbox <= 0 || u_blocks <= 0 || fine_blocks <= 0 || restrict_blocks <= 0) return hipErrorInvalidValue;
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    if (gc)
+      hipLaunchKernelGGL((ho_flux_kernel<PR, true, false>), dim3(u_blocks, nbox), dim3(256), 0, stream, d_boxes, box0,
+                         parity);
+    else
+      hipLaunchKernelGGL((ho_flux_kernel<PR, false, false>), dim3(u_blocks, nbox), dim3(256), 0, stream, d_boxes, box0,
+                         parity);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fine_flux_kernel<PR>), dim3(fine_blocks, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((fine_phase_kernel<PR>), dim3(fine_blocks, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((fine_restrict_kernel<PR>), dim3(restrict_blocks, nbox), dim3(256), 0, stream, d_boxes, box0,
+                       1 - parity);
     return hipGetLastError();
   });
 }

@@ -75,6 +75,29 @@ hipError_t launch_high_order_phase(int precision, bool gc, bool literal, const B
 int high_order_blocks_per_box(int64_t max_nodes);
 int high_order_phase_tiles(int nx, int ny, int nz);
 
+// Finer phase-field grid (LBM_FINE_PHASE), boxes with fphi / fgrid / aux
+// (3 planes) allocated.
+// launch_fine_init: fine phi of buffer `parity` interpolated from the coarse
+// phi, then the coarse phi replaced by the restriction (d_box: this box's
+// device descriptor).  launch_fine_set: fine phi from 8 N doubles (fine
+// layout [2nz][2ny][2nx]), then the restriction.  launch_fine_get: fine phi
+// decoded into 8 N doubles.
+hipError_t launch_fine_init(int precision, const BoxDesc& box, const BoxDesc* d_box, int parity, hipStream_t stream);
+hipError_t launch_fine_set(int precision, const BoxDesc& box, const BoxDesc* d_box, int parity, const double* d_src,
+                           hipStream_t stream);
+hipError_t launch_fine_get(int precision, const BoxDesc& box, int parity, double* d_dst, hipStream_t stream);
+// The phase update of a step on the fine grids of boxes box0 .. box0 + nbox
+// - 1: reads level `parity` (coarse state and fine phi), writes the fine phi
+// of buffer 1 - parity and overwrites the coarse phi of buffer 1 - parity
+// with its restriction.  Runs after the fused step of the same parity.
+// u_blocks: high_order_blocks_per_box of the largest box; fine_blocks:
+// fine_blocks_per_box of the largest fine_units; restrict_blocks: workgroups
+// per box of the restriction.
+hipError_t launch_fine_phase(int precision, bool gc, const BoxDesc* d_boxes, int box0, int nbox, int parity,
+                             int u_blocks, int fine_blocks, int restrict_blocks, hipStream_t stream);
+int64_t fine_units(int nx, int ny, int nz);
+int fine_blocks_per_box(int64_t max_units);
+
 constexpr int kDiagValues = 28;
 constexpr int kDiagBlocks = 1024;
 // Workgroups per box of the diagnostics launch for boxes of at most

@@ -100,6 +100,8 @@ extern "C" lbm_status lbm_step_noalloc(const lbm_params* box, const lbm_tuning* 
   if (s != LBM_OK) return s;
   if (box->flags & LBM_HIGH_ORDER_AC)
     return set_error(LBM_ERR_UNSUPPORTED, "%s: LBM_HIGH_ORDER_AC needs per-box device buffers; use a context", who);
+  if (box->flags & LBM_FINE_PHASE)
+    return set_error(LBM_ERR_UNSUPPORTED, "%s: LBM_FINE_PHASE needs per-box device buffers; use a context", who);
   if (!phi || !mom) return set_error(LBM_ERR_ARG, "%s: phi / mom buffer arrays are NULL", who);
   const int prec = box->precision;
   const size_t ep = prec == LBM_FP64 ? 8 : 4;

@@ -31,7 +31,9 @@ struct Box {
   lbm_params prm{};
   BoxDesc desc{};
   void* mem[2] = {nullptr, nullptr};
-  void* aux = nullptr;  // LBM_HIGH_ORDER_AC: 6 planes of n doubles
+  void* aux = nullptr;  // LBM_HIGH_ORDER_AC: 6 planes of n doubles; LBM_FINE_PHASE: 3
+  void* fmem[2] = {nullptr, nullptr};  // LBM_FINE_PHASE: fine phi per parity
+  void* fgrid = nullptr;               // LBM_FINE_PHASE: fine flux (padded grid)
   int64_t n = 0;
   bool initialized = false;
   double enc_off[10] = {0};
@@ -48,6 +50,10 @@ struct lbm_ctx {
   bool ho_lit = false;  // with LBM_HIGH_ORDER_AC: LBM_LITERAL_ADVECTION (all boxes)
   int ho_bpb = 1;   // workgroups per box of the fourth-order flux kernel
   int ho_tiles = 1; // workgroups per box of the fourth-order phase kernel (largest box)
+  bool fine = false;   // LBM_FINE_PHASE (all boxes)
+  int fine_u_bpb = 1;  // with LBM_FINE_PHASE: workgroups per box of the coarse velocity kernel,
+  int fine_bpb = 1;    // of the fine flux and phase kernels
+  int fine_rbpb = 1;   // and of the restriction
   hipStream_t stream = nullptr;
   bool own_stream = false;
   lbm_device dev{};
@@ -119,7 +125,9 @@ lbm_status validate_box(const lbm_params& p, int idx, int precision0, const char
   }
   if (p.precision < LBM_FP64 || p.precision > LBM_BF16_OS) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: precision %d invalid", who, idx, p.precision);
   if (p.precision != precision0) return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: all boxes of a context must share one precision", who, idx);
-  if (p.flags & ~(LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE | LBM_HIGH_ORDER_AC)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: unknown flags 0x%x", who, idx, p.flags);
+  if (p.flags & ~(LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE | LBM_HIGH_ORDER_AC | LBM_FINE_PHASE)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: unknown flags 0x%x", who, idx, p.flags);
+  if ((p.flags & LBM_FINE_PHASE) && (p.flags & (LBM_HIGH_ORDER_AC | LBM_LITERAL_ADVECTION)))
+    return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: LBM_FINE_PHASE is not combined with LBM_HIGH_ORDER_AC or LBM_LITERAL_ADVECTION", who, idx);
   if (p.flags & LBM_HIGH_ORDER_AC)
     for (int a = 0; a < 3; ++a)
       if (p.bc[a] == LBM_WALL && d[a] < 4) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: wall axis %d needs >= 4 nodes with LBM_HIGH_ORDER_AC", who, idx, a);
@@ -220,6 +228,11 @@ hipError_t enqueue_steps(lbm_ctx* c, int nsteps, int parity0) {
     if (c->ho) {
       e = lbm::launch_high_order_phase(c->precision, c->gc, c->ho_lit, c->d_boxes, 0, static_cast<int>(c->boxes.size()),
                                        parity, c->ho_bpb, c->ho_tiles, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    if (c->fine) {
+      e = lbm::launch_fine_phase(c->precision, c->gc, c->d_boxes, 0, static_cast<int>(c->boxes.size()), parity,
+                                 c->fine_u_bpb, c->fine_bpb, c->fine_rbpb, c->stream);
       if (e != hipSuccess) return e;
     }
     parity ^= 1;
@@ -413,6 +426,8 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
         return fail(nullptr, LBM_ERR_UNSUPPORTED, "lbm_create: box %d: all boxes of a context must share one closure", i);
       if ((boxes[i].flags ^ boxes[0].flags) & LBM_HIGH_ORDER_AC)
         return fail(nullptr, LBM_ERR_UNSUPPORTED, "lbm_create: box %d: all boxes of a context must share LBM_HIGH_ORDER_AC", i);
+      if ((boxes[i].flags ^ boxes[0].flags) & LBM_FINE_PHASE)
+        return fail(nullptr, LBM_ERR_UNSUPPORTED, "lbm_create: box %d: all boxes of a context must share LBM_FINE_PHASE", i);
       if ((boxes[0].flags & LBM_HIGH_ORDER_AC) && ((boxes[i].flags ^ boxes[0].flags) & LBM_LITERAL_ADVECTION))
         return fail(nullptr, LBM_ERR_UNSUPPORTED,
                     "lbm_create: box %d: with LBM_HIGH_ORDER_AC all boxes must share LBM_LITERAL_ADVECTION", i);
@@ -426,6 +441,7 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
     c->gc = (boxes[0].flags & LBM_GRADIENT_CLOSURE) != 0;
     c->ho = (boxes[0].flags & LBM_HIGH_ORDER_AC) != 0;
     c->ho_lit = c->ho && (boxes[0].flags & LBM_LITERAL_ADVECTION) != 0;
+    c->fine = (boxes[0].flags & LBM_FINE_PHASE) != 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) {
       delete c;
@@ -468,6 +484,20 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
         }
         b.desc.aux = static_cast<double*>(b.aux);
       }
+      if (c->fine) {
+        const int64_t nf = 8 * b.n;
+        const int64_t np = static_cast<int64_t>(2 * b.prm.nx + 2) * (2 * b.prm.ny + 2) * (2 * b.prm.nz + 2);
+        b.aux = dev_alloc(c, align256(static_cast<size_t>(b.n) * 3 * sizeof(double)));
+        b.fgrid = dev_alloc(c, align256(static_cast<size_t>(np) * 3 * sizeof(double)));
+        for (int s = 0; s < 2; ++s) b.fmem[s] = dev_alloc(c, align256(lbm::phi_bytes(c->precision, nf)));
+        if (!b.aux || !b.fgrid || !b.fmem[0] || !b.fmem[1]) {
+          lbm_destroy(c);
+          return fail(nullptr, LBM_ERR_OOM, "lbm_create: fine phase-field buffer allocation failed (box %d)", i);
+        }
+        b.desc.aux = static_cast<double*>(b.aux);
+        b.desc.fgrid = static_cast<double*>(b.fgrid);
+        for (int s = 0; s < 2; ++s) b.desc.fphi[s] = b.fmem[s];
+      }
     }
     c->d_boxes = static_cast<BoxDesc*>(dev_alloc(c, align256(n_boxes * sizeof(BoxDesc))));
     int64_t max_n = 1;
@@ -476,6 +506,13 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
     c->ho_bpb = lbm::high_order_blocks_per_box(max_n);
     for (auto& b : c->boxes)
       c->ho_tiles = std::max(c->ho_tiles, lbm::high_order_phase_tiles(b.prm.nx, b.prm.ny, b.prm.nz));
+    if (c->fine) {
+      int64_t max_units = 1;
+      for (auto& b : c->boxes) max_units = std::max(max_units, lbm::fine_units(b.prm.nx, b.prm.ny, b.prm.nz));
+      c->fine_u_bpb = lbm::high_order_blocks_per_box(max_n);
+      c->fine_bpb = lbm::fine_blocks_per_box(max_units);
+      c->fine_rbpb = static_cast<int>(std::min<int64_t>(4096, (max_n + 255) / 256));
+    }
     c->d_diag = static_cast<double*>(dev_alloc(
         c, align256(static_cast<size_t>(n_boxes) * (c->diag_bpb + 1) * lbm::kDiagValues * sizeof(double))));
     if (!c->d_boxes || !c->d_diag) {
@@ -521,6 +558,10 @@ lbm_status lbm_init_phase(lbm_ctx* c, int32_t box, const double* phi, const doub
     if ((s = put_field(c, b, 2 + a, u ? u + a * b.n : nullptr)) != LBM_OK) return s;
   for (int k = 5; k < kFields; ++k)
     if ((s = put_field(c, b, k, nullptr)) != LBM_OK) return s;
+  if (c->fine) {
+    HIP_TRY(c, lbm::launch_fine_init(c->precision, b.desc, c->d_boxes + box, c->parity, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   b.initialized = true;
   return LBM_OK;
 }
@@ -533,7 +574,42 @@ lbm_status lbm_set_state(lbm_ctx* c, int32_t box, const double* state) {
   if ((s = ensure_stage(c, b.n)) != LBM_OK) return s;
   for (int k = 0; k < kFields; ++k)
     if ((s = put_field(c, b, k, state + k * b.n)) != LBM_OK) return s;
+  if (c->fine) {
+    HIP_TRY(c, lbm::launch_fine_init(c->precision, b.desc, c->d_boxes + box, c->parity, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   b.initialized = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_fine_phase(lbm_ctx* c, int32_t box, double* out) {
+  lbm_status s = check_box(c, box);
+  if (s != LBM_OK) return s;
+  if (!out) return fail(c, LBM_ERR_ARG, "lbm_get_fine_phase: out is NULL");
+  if (!c->fine) return fail(c, LBM_ERR_UNSUPPORTED, "lbm_get_fine_phase: the context has no LBM_FINE_PHASE");
+  Box& b = c->boxes[box];
+  if (!b.initialized) return fail(c, LBM_ERR_STATE, "lbm_get_fine_phase: box %d not initialised", box);
+  const int64_t nf = 8 * b.n;
+  if ((s = ensure_stage(c, nf)) != LBM_OK) return s;
+  HIP_TRY(c, lbm::launch_fine_get(c->precision, b.desc, c->parity, c->d_stage, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(out, c->d_stage, nf * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (!all_finite(out, nf)) return fail(c, LBM_ERR_UNSTABLE, "lbm_get_fine_phase: non-finite values in box %d", box);
+  return LBM_OK;
+}
+
+lbm_status lbm_set_fine_phase(lbm_ctx* c, int32_t box, const double* in) {
+  lbm_status s = check_box(c, box);
+  if (s != LBM_OK) return s;
+  if (!in) return fail(c, LBM_ERR_ARG, "lbm_set_fine_phase: in is NULL");
+  if (!c->fine) return fail(c, LBM_ERR_UNSUPPORTED, "lbm_set_fine_phase: the context has no LBM_FINE_PHASE");
+  Box& b = c->boxes[box];
+  if (!b.initialized) return fail(c, LBM_ERR_STATE, "lbm_set_fine_phase: box %d holds no state", box);
+  const int64_t nf = 8 * b.n;
+  if ((s = ensure_stage(c, nf)) != LBM_OK) return s;
+  HIP_TRY(c, hipMemcpyAsync(c->d_stage, in, nf * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, lbm::launch_fine_set(c->precision, b.desc, c->d_boxes + box, c->parity, c->d_stage, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 
@@ -610,6 +686,9 @@ lbm_status lbm_step_unbatched(lbm_ctx* c, int32_t nsteps) {
       if (c->ho)
         HIP_TRY(c, lbm::launch_high_order_phase(c->precision, c->gc, c->ho_lit, c->d_boxes, static_cast<int>(k), 1,
                                                 c->parity, c->ho_bpb, c->ho_tiles, c->stream));
+      if (c->fine)
+        HIP_TRY(c, lbm::launch_fine_phase(c->precision, c->gc, c->d_boxes, static_cast<int>(k), 1, c->parity,
+                                          c->fine_u_bpb, c->fine_bpb, c->fine_rbpb, c->stream));
     }
     c->parity ^= 1;
   }
@@ -855,7 +934,9 @@ void lbm_destroy(lbm_ctx* c) {
   drop_graphs(c);
   for (auto& b : c->boxes) {
     for (int s = 0; s < 2; ++s) dev_free(c, b.mem[s]);
+    for (int s = 0; s < 2; ++s) dev_free(c, b.fmem[s]);
     dev_free(c, b.aux);
+    dev_free(c, b.fgrid);
   }
   dev_free(c, c->d_boxes);
   dev_free(c, c->d_items);

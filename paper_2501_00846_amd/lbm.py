@@ -27,6 +27,7 @@ PERIODIC, WALL = 0, 1
 LITERAL_ADVECTION = 1
 GRADIENT_CLOSURE = 2
 HIGH_ORDER_AC = 4
+FINE_PHASE = 8
 FIELDS = ("phi", "P", "Jx", "Jy", "Jz", "Qxx", "Qyy", "Qzz", "Qxy", "Qxz", "Qyz")
 
 
@@ -86,6 +87,8 @@ _SIGS = {
     "lbm_diagnostics_all": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(lbm_diag)]),
     "lbm_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "lbm_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "lbm_get_fine_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "lbm_set_fine_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "lbm_get_state_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                             ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_set_encoding": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -150,7 +153,8 @@ def make_params(prob, precision="fp64"):
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.flags = (LITERAL_ADVECTION if getattr(prob, "literal_advection", False) else 0) | \
         (GRADIENT_CLOSURE if getattr(prob, "gradient_closure", False) else 0) | \
-        (HIGH_ORDER_AC if getattr(prob, "high_order_ac", False) else 0)
+        (HIGH_ORDER_AC if getattr(prob, "high_order_ac", False) else 0) | \
+        (FINE_PHASE if getattr(prob, "fine_phase", False) else 0)
     p.rho_l, p.rho_g = float(prob.rho_l), float(prob.rho_g)
     p.nu_l, p.nu_g = float(prob.nu_l), float(prob.nu_g)
     p.sigma, p.mobility, p.width = float(prob.sigma), float(prob.mobility), float(prob.width)
@@ -220,6 +224,16 @@ def lbm_get_state(ctx, box, n):
     st = np.empty(11 * n)
     _check(load_library().lbm_get_state(ctx, box, _ptr(st)), ctx)
     return st
+
+
+def lbm_get_fine_phase(ctx, box, n):
+    out = np.empty(8 * n)
+    _check(load_library().lbm_get_fine_phase(ctx, box, _ptr(out)), ctx)
+    return out
+
+
+def lbm_set_fine_phase(ctx, box, n, phif):
+    _check(load_library().lbm_set_fine_phase(ctx, box, _ptr(_f64(phif, 8 * n))), ctx)
 
 
 def lbm_get_state_points(ctx, box, nodes):
@@ -366,6 +380,14 @@ class Context:
     def get_state(self, box):
         p = self.problems[box]
         return lbm_get_state(self.ctx, box, self.sizes[box]).reshape(11, p.nz, p.ny, p.nx)
+
+    def get_fine_phase(self, box):
+        """The fine phase field (LBM_FINE_PHASE) as (2nz, 2ny, 2nx)."""
+        p = self.problems[box]
+        return lbm_get_fine_phase(self.ctx, box, self.sizes[box]).reshape(2 * p.nz, 2 * p.ny, 2 * p.nx)
+
+    def set_fine_phase(self, box, phif):
+        lbm_set_fine_phase(self.ctx, box, self.sizes[box], phif)
 
     def state_at(self, box, points):
         """11 decoded state values at (x, y, z) points -> (11, n)."""

@@ -56,7 +56,7 @@ def _create(params, n=None):
     (dict(sigma=-1.0), -1, "sigma"),
     (dict(mobility=-0.1), -1, "mobility"),
     (dict(precision=7), -1, "precision"),
-    (dict(flags=8), -1, "flags"),
+    (dict(flags=16), -1, "flags"),
 ])
 def test_create_rejects_bad_parameters(kw, code, frag):
     st, out, msg = _create([_params(**kw)])
@@ -186,3 +186,17 @@ def test_high_order_variant_needs_four_nodes_on_wall_axes():
     assert _noalloc(p3)[0] == -2
     st, _, msg = _create([_params(flags=4), _params(flags=5)])  # printed advection in one box only
     assert st == -2 and "LBM_LITERAL_ADVECTION" in msg
+
+
+def test_fine_phase_variant_checks():
+    """LBM_FINE_PHASE (8): shared by every box of a context, not combined with
+    the fourth-order update or the printed advection, not through
+    lbm_step_noalloc (all checked before any device call)."""
+    st, _, msg = _create([_params(flags=8), _params()])
+    assert st == -2 and "LBM_FINE_PHASE" in msg
+    st, _, msg = _create([_params(flags=8 | 4)])
+    assert st == -2 and "LBM_FINE_PHASE" in msg
+    st, _, msg = _create([_params(flags=8 | 1)])
+    assert st == -2 and "LBM_FINE_PHASE" in msg
+    st, msg = _noalloc(_params(flags=8))
+    assert st == -2 and "LBM_FINE_PHASE" in msg

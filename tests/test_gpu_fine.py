@@ -1,0 +1,200 @@
+"""Finer phase-field grid (LBM_FINE_PHASE) on the GPU against the FP64
+oracle's variant (readings F1-F6 of oracle/scheme.py), through the C ABI:
+the coarse state and the fine phase field after one step, after 100 steps,
+and the invariants (phase mass, restriction, restarts, ensembles)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import scheme as S
+from paper_2501_00846_amd import lbm, workloads
+from paper_2501_00846_amd.workloads import PERIODIC, WALL, Problem
+from tests.gpu_util import (array_state, field_tolerance, quantize_state, rel_err, smooth_random_state,
+                            state_array, FIELDS)
+
+pytestmark = pytest.mark.gpu
+P_, W_ = PERIODIC, WALL
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _prob(dims, bc, **kw):
+    base = dict(rho_l=1.0, rho_g=0.01, nu_l=0.02, nu_g=0.1, sigma=0.01, mobility=0.05, width=3.0,
+                gravity=(1e-5, -2e-5, 3e-5), rho_ref=0.5, fine_phase=True)
+    base.update(kw)
+    return Problem(*dims, bc=bc, **base)
+
+
+def _fine_field(prob, seed):
+    """Smooth random fine phase field in (0, 1) at the fine node positions."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*(np.arange(2 * n) / 2.0 - 0.25 for n in prob.shape), indexing="ij")
+    k = rng.uniform(0.3, 1.1, size=(3, 3))
+    ph = rng.uniform(0, 2 * np.pi, size=3)
+    arg = sum(np.sin(k[i, 0] * x + k[i, 1] * y + k[i, 2] * z + ph[i]) for i in range(3)) / 3.0
+    return 0.5 + 0.45 * arg + 0.02 * rng.uniform(-1, 1, z.shape)
+
+
+def _gpu(prob, state, phif, nsteps, precision="fp64"):
+    with lbm.Context(prob, precision) as ctx:
+        ctx.set_state(0, state.reshape(-1))
+        ctx.set_fine_phase(0, phif.reshape(-1))
+        ctx.step(nsteps)
+        return ctx.get_state(0), ctx.get_fine_phase(0)
+
+
+def _oracle(prob, state, phif, nsteps):
+    st = array_state(state)
+    st.phi = S.restrict(phif)
+    st, phif = S.run_fine(st, phif, prob, nsteps)
+    return state_array(st), phif
+
+
+def _fine_err(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+GRIDS = [
+    ((19, 15, 12), (P_, P_, P_)),
+    ((19, 15, 12), (W_, P_, W_)),
+    ((17, 9, 7), (W_, W_, W_)),
+    ((2, 3, 4), (W_, W_, W_)),     # wall axes at their minimum of 2 nodes
+    ((3, 1, 5), (P_, P_, P_)),     # one node on an axis: the fine axis has 2
+    ((40, 5, 3), (P_, W_, P_)),
+]
+
+
+@pytest.mark.parametrize("dims,bc", GRIDS)
+def test_one_step_fp64(dims, bc):
+    prob = _prob(dims, bc)
+    state = smooth_random_state(prob, seed=sum(dims) + 11)
+    phif = _fine_field(prob, seed=sum(dims) + 12)
+    _log("fine phase one step fp64 %s bc=%s" % (dims, bc))
+    got, gotf = _gpu(prob, state, phif, 1)
+    ref, reff = _oracle(prob, state, phif, 1)
+    err = rel_err(got, ref)
+    assert max(err.values()) <= 1e-12, err
+    assert _fine_err(gotf, reff) <= 1e-12
+
+
+def test_one_step_fp64_gradient_closure():
+    prob = _prob((21, 17, 9), (P_, W_, W_), gradient_closure=True)
+    state = smooth_random_state(prob, seed=17)
+    state[5:] = 0.0  # the gradient closure keeps no Q
+    phif = _fine_field(prob, seed=18)
+    got, gotf = _gpu(prob, state, phif, 2)
+    ref, reff = _oracle(prob, state, phif, 2)
+    err = rel_err(got, ref)
+    assert max(err.values()) <= 1e-12, err
+    assert _fine_err(gotf, reff) <= 1e-12
+
+
+def test_initial_phi_is_interpolated_and_restricted():
+    """A coarse phi given at initialisation: the fine field is its trilinear
+    interpolation and the coarse phi becomes the restriction of that (F6)."""
+    prob = _prob((13, 10, 8), (W_, P_, W_))
+    state = smooth_random_state(prob, seed=23)
+    with lbm.Context(prob, "fp64") as ctx:
+        ctx.set_state(0, state.reshape(-1))
+        phif = ctx.get_fine_phase(0)
+        phic = ctx.get_state(0)[0]
+    expect_f = S.prolong(state[0], prob)
+    assert np.abs(phif - expect_f).max() <= 1e-15
+    assert np.abs(phic - S.restrict(expect_f)).max() <= 1e-15
+
+
+@pytest.mark.parametrize("case_name", ["droplet", "walled_bubble"])
+def test_100_steps_fp64(case_name):
+    """100 FP64 steps from a workload's initial fields match the oracle
+    within 1e-10 (relative L2 and max) on rho, u, phi, p and the fine phi: a
+    static droplet at density ratio 1000 (periodic) and a buoyant bubble
+    between walls."""
+    if case_name == "droplet":
+        case = workloads.static_droplet(n=24, radius=6.0, seed=3, noise=1e-5)
+    else:
+        case = workloads.rising_bubble(nx=24, ny=20, nz=40, radius=6.0, zc=14.0, seed=9)
+    case.problem.fine_phase = True
+    prob = case.problem
+    _log("fine phase %s 100 steps fp64" % case_name)
+    with lbm.Context(prob, "fp64") as ctx:
+        ctx.init_case(0, case)
+        ctx.step(100)
+        f = ctx.fields(0)
+        gotf = ctx.get_fine_phase(0)
+    phif, phic = S.initial_fine_phase(case.phi, prob)
+    st, reff = S.run_fine(S.initial_state(phic, case.u, case.pstar), phif, prob, 100)
+    ob = S.observables(st, prob)
+    for name in ("rho", "phi", "u", "p"):
+        a, b = f[name], ob[name]
+        l2 = np.linalg.norm(a - b) / np.linalg.norm(b)
+        mx = np.abs(a - b).max() / np.abs(b).max()
+        assert l2 <= 1e-10 and mx <= 1e-10, (name, l2, mx)
+    assert np.linalg.norm(gotf - reff) / np.linalg.norm(reff) <= 1e-10
+    assert _fine_err(gotf, reff) <= 1e-10
+
+
+def test_one_step_fp32():
+    """FP32 storage (coarse state and fine phi in FP32): one step matches the
+    oracle run from the host-quantised inputs within the FP32 tolerance."""
+    prob = _prob((17, 9, 7), (W_, W_, W_), rho_g=1e-3, nu_l=1 / 60, nu_g=1 / 6,
+                 gravity=(0.0, 0.0, -1e-5), rho_ref=1.0)
+    state = quantize_state(smooth_random_state(prob, seed=31), "fp32")
+    phif = _fine_field(prob, seed=32).astype(np.float32).astype(np.float64)
+    got, gotf = _gpu(prob, state, phif, 1, "fp32")
+    ref, reff = _oracle(prob, state, phif, 1)
+    tol = field_tolerance("fp32", ref)
+    for k, name in enumerate(FIELDS):
+        worst = float((np.abs(got[k] - ref[k]) / tol[k]).max())
+        assert worst <= 1.0, (name, worst)
+    assert _fine_err(gotf, reff) <= 2e-5
+
+
+def test_phase_mass_conserved_with_walls():
+    """The fine phase mass is conserved to round-off over 200 steps with
+    walls on every axis (F5), and the coarse phase mass is one eighth of it
+    (the restriction, F2)."""
+    prob = _prob((14, 12, 16), (W_, W_, W_))
+    state = smooth_random_state(prob, seed=8)
+    with lbm.Context(prob, "fp64") as ctx:
+        ctx.set_state(0, state.reshape(-1))
+        m0 = ctx.get_fine_phase(0).sum()
+        ctx.step(200)
+        m1 = ctx.get_fine_phase(0).sum()
+        mc = ctx.diagnostics(0)["phase_mass"]
+    assert abs(m1 - m0) <= 1e-12 * abs(m0), (m0, m1)
+    assert abs(mc - m1 / 8.0) <= 1e-12 * abs(mc), (mc, m1)
+
+
+def test_restart_from_state_and_fine_field_is_exact():
+    """Five steps equal three steps, a restart of a new context from the
+    coarse state and the fine field read back, and two more steps (bitwise)."""
+    prob = _prob((19, 15, 12), (W_, P_, W_))
+    state = smooth_random_state(prob, seed=41)
+    phif = _fine_field(prob, seed=42)
+    straight, straight_f = _gpu(prob, state, phif, 5)
+    mid, mid_f = _gpu(prob, state, phif, 3)
+    again, again_f = _gpu(prob, mid, mid_f, 2)
+    assert np.array_equal(again, straight)
+    assert np.array_equal(again_f, straight_f)
+
+
+def test_ensemble_one_launch_equals_separate_boxes():
+    """Two boxes in one context (one launch of each kernel per step) give
+    bitwise the results of each box run alone."""
+    probs = [_prob((12, 10, 9), (P_, P_, P_)), _prob((19, 15, 12), (P_, W_, W_))]
+    states = [smooth_random_state(p, seed=60 + i) for i, p in enumerate(probs)]
+    fines = [_fine_field(p, seed=70 + i) for i, p in enumerate(probs)]
+    with lbm.Context(probs, "fp64") as ctx:
+        for i, s in enumerate(states):
+            ctx.set_state(i, s.reshape(-1))
+            ctx.set_fine_phase(i, fines[i].reshape(-1))
+        ctx.step(3)
+        together = [(ctx.get_state(i), ctx.get_fine_phase(i)) for i in range(2)]
+    for i, p in enumerate(probs):
+        alone = _gpu(p, states[i], fines[i], 3)
+        assert np.array_equal(together[i][0], alone[0]), i
+        assert np.array_equal(together[i][1], alone[1]), i
