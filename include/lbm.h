@@ -108,8 +108,8 @@ enum {
    * lbm_set_fine_phase read and write the fine field itself.  The diffusive
    * part is stable for 4 * mobility below about 0.35.  Each box keeps two
    * fine phi buffers (8 N values of the phi storage type each), the flux of a
-   * step (3 (2nx+2)(2ny+2)(2nz+2) doubles) and the coarse velocity (3 N
-   * doubles); a step runs four more kernels.  All boxes of a context must
+   * step (3 (2nx+2)(2ny+2)(2nz+2) values of that type) and the coarse
+   * velocity (3 N doubles); a step runs four more kernels.  All boxes of a context must
    * agree on this flag; not combined with LBM_HIGH_ORDER_AC or
    * LBM_LITERAL_ADVECTION, and not available through lbm_step_noalloc. */
   LBM_FINE_PHASE = 8

@@ -780,7 +780,8 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
 // of its cell.  After the fused step of a step, reading level n:
 //   ho_flux_kernel<PR, GC, false>  coarse u = J + a/2 into b.aux;
 //   fine_flux_kernel   G = phi u_f + (4M/W) phi (1 - phi) n over the fine grid
-//                      grown by one ghost layer (b.fgrid), u_f the trilinear
+//                      grown by one ghost layer (b.fgrid, in the phi storage
+//                      type), u_f the trilinear
 //                      interpolation of the coarse u, n from the isotropic
 //                      gradient at spacing h;
 //   fine_phase_kernel  phi_f' = phi_f - div_h G + M lap_h phi_f into the other
@@ -882,163 +883,258 @@ __global__ void fine_decode_kernel(BoxDesc b, int s, double* __restrict__ dst, i
     dst[i] = dec<double>(fphi[i], 0.f, 1.f);
 }
 
-// Work units of fine_flux_kernel per box: one padded column over a chunk of
-// up to kHoZ fine planes, plus the two ghost planes of every column.
-__host__ __device__ inline int64_t fine_flux_units(int nx, int ny, int nz) {
-  return static_cast<int64_t>(2 * nx + 2) * (2 * ny + 2) * ((2 * nz + kHoZ - 1) / kHoZ + 2);
-}
-__host__ __device__ inline int64_t fine_phase_units(int nx, int ny, int nz) {
-  return static_cast<int64_t>(2 * nx) * (2 * ny) * ((2 * nz + kHoZ - 1) / kHoZ);
+// The flux G at every node of the fine grid grown by one ghost layer.  A
+// workgroup of 256 threads owns a tile of kFnTX x kFnTY padded columns and
+// marches it over up to kHoZ padded planes.  Per plane it stages, with a
+// one-column halo, the fine phi continued across the boundary (mirrored
+// beyond a wall, wrapped on a periodic axis) in LDS; each thread filters its
+// column in x and y and keeps the filtered planes z-1, z, z+1 in registers.
+// On the continued field the gradient at a ghost node is the mirror node's
+// with the crossed components negated, as the ghost rule asks; the velocity
+// there is the interpolation at the mirror node, negated per crossed wall.
+constexpr int kFnTX = 32, kFnTY = 8;
+constexpr int kFnPX = kFnTX + 2, kFnPY = kFnTY + 2, kFnNP = kFnPX * kFnPY;
+
+__host__ __device__ inline int fine_flux_tiles(int nx, int ny, int nz) {
+  return ((2 * nx + 2 + kFnTX - 1) / kFnTX) * ((2 * ny + 2 + kFnTY - 1) / kFnTY) * ((2 * nz + 2 + kHoZ - 1) / kHoZ);
 }
 
-// The flux G at every node of the padded fine grid.  A unit marches its
-// source column (the mirror or periodic image of a ghost column) over its
-// planes with the x-y filtered phi planes z-1, z, z+1 in registers; a ghost
-// plane is a unit of one plane at its source plane.
 template <class PR>
 __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
   using TP = typename PR::TP;
+  __shared__ double sP[kFnNP];
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   const int nx = b.nx, ny = b.ny;
   const int fx = 2 * nx, fy = 2 * ny, fz = 2 * b.nz;
-  const int px = fx + 2, py = fy + 2;
-  const int64_t ncolp = static_cast<int64_t>(px) * py;
-  const int nch = (fz + kHoZ - 1) / kHoZ;
-  const int64_t units = ncolp * (nch + 2);
+  const int px = fx + 2, py = fy + 2, pz = fz + 2;
+  const int ntx = (px + kFnTX - 1) / kFnTX, nty = (py + kFnTY - 1) / kFnTY;
+  const int tiles = ntx * nty * ((pz + kHoZ - 1) / kHoZ);
   const int64_t n = static_cast<int64_t>(nx) * ny * b.nz;
   const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
   const double* __restrict__ u = b.aux;
-  double* __restrict__ G = b.fgrid;
+  const gptr<TP> G = (gptr<TP>)b.fgrid;
   const double kac = b.kappa_ac;
   constexpr double kInvH = 2.0;  // 1 / h
-  for (int64_t un = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; un < units;
-       un += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t col = un % ncolp;
-    const int ch = static_cast<int>(un / ncolp);
-    const int Xp = static_cast<int>(col % px), Yp = static_cast<int>(col / px);
-    int kxs, kys, kzs = 0;
+  const int tid = threadIdx.x;
+  const int lx = tid % kFnTX, ly = tid / kFnTX;
+  for (int t = blockIdx.x; t < tiles; t += gridDim.x) {  // uniform over the workgroup
+    const int xp0 = (t % ntx) * kFnTX, yp0 = ((t / ntx) % nty) * kFnTY, zp0 = (t / (ntx * nty)) * kHoZ;
+    const int zp1 = min(zp0 + kHoZ, pz);
+    const int Xp = xp0 + lx, Yp = yp0 + ly;
+    const bool active = Xp < px && Yp < py;
+    // the mirror (or periodic image) column of this padded column
+    int kxs, kys;
     const int xm = map_axis(Xp - 1, fx, b.wall[0], kxs);
     const int ym = map_axis(Yp - 1, fy, b.wall[1], kys);
-    int zs, ze, zd;
-    if (ch < nch) {
-      zs = ch * kHoZ;
-      ze = min(zs + kHoZ, fz);
-      zd = zs + 1;
-    } else if (ch == nch) {
-      zs = map_axis(-1, fz, b.wall[2], kzs);
-      ze = zs + 1;
-      zd = 0;
-    } else {
-      zs = map_axis(fz, fz, b.wall[2], kzs);
-      ze = zs + 1;
-      zd = fz + 1;
-    }
-    int xs[3], ys[3];
-    for (int c = -1; c <= 1; ++c) {
-      xs[c + 1] = map_axis(xm + c, fx, b.wall[0]);
-      ys[c + 1] = map_axis(ym + c, fy, b.wall[1]);
-    }
-    TP r[9];
-    auto issue = [&](int q) {
-      const int zq = map_axis(q, fz, b.wall[2]);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) r[k] = fphi[fine_at(b, xs[k % 3], ys[k / 3], zq)];
-    };
-    auto filt = [&](double F[4]) {
-      auto ld = [&](int, int, int cx, int cy) { return dec<double>(r[cy * 3 + cx], 0.f, 1.f); };
-      diag_filter(ld, xs, ys, F);
-    };
-    // signs of the destination (ghost) node: u negated per crossed wall, the
-    // crossed components of the normal negated
-    const double su = ((kxs + kys + kzs) & 1) ? -1.0 : 1.0;
-    const double tn[3] = {kxs ? -1.0 : 1.0, kys ? -1.0 : 1.0, kzs ? -1.0 : 1.0};
-    double F[3][4];
-    issue(zs - 1);
-    filt(F[0]);
-    issue(zs);
-    filt(F[1]);
-    issue(zs + 1);
-    for (int z = zs; z < ze; ++z) {
-      filt(F[2]);  // plane z + 1
-      if (z + 1 < ze) issue(z + 2);
-      const double phi = F[1][3];
-      const double g[3] = {(F[0][1] + 4.0 * F[1][1] + F[2][1]) * (kInvH / 72.0),
-                           (F[0][2] + 4.0 * F[1][2] + F[2][2]) * (kInvH / 72.0), (F[2][0] - F[0][0]) * (kInvH / 72.0)};
-      const double inv = 1.0 / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + 1e-12);
-      const double pp = phi * (1.0 - phi);
+    // the trilinear interpolation of u at the mirror column, split as the x-y
+    // (bilinear) sum over its four coarse neighbours per coarse plane -- each
+    // coarse plane summed once per march and used by the fine planes around
+    // it -- then 3/4 and 1/4 along z.  A coarse ghost beyond a wall is minus
+    // its mirror node.
+    int ux[2], uy[2], ukx[2] = {0, 0}, uky[2] = {0, 0};
+    ux[0] = xm >> 1;
+    uy[0] = ym >> 1;
+    ux[1] = map_axis(ux[0] + ((xm & 1) ? 1 : -1), nx, b.wall[0], ukx[1]);
+    uy[1] = map_axis(uy[0] + ((ym & 1) ? 1 : -1), ny, b.wall[1], uky[1]);
+    auto coarse_plane = [&](int p, double B[3]) {
+      int kz;
+      const int pm = map_axis(p, b.nz, b.wall[2], kz);
       for (int a = 0; a < 3; ++a) {
-        auto ldu = [&](int x, int y, int zc) { return u[a * n + (static_cast<int64_t>(zc) * ny + y) * nx + x]; };
-        const double uf = interp_fine<true>(b, xm, ym, z, ldu);
-        G[fgrid_at(b, a, Xp, Yp, zd + (z - zs))] = su * phi * uf + kac * (tn[a] * pp * g[a] * inv);
+        double acc = 0.0;
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const double w = (dx ? 0.25 : 0.75) * (dy ? 0.25 : 0.75);
+            const double v = u[a * n + (static_cast<int64_t>(pm) * ny + uy[dy]) * nx + ux[dx]];
+            acc += ((ukx[dx] + uky[dy] + kz) & 1) ? -w * v : w * v;
+          }
+        B[a] = acc;
       }
+    };
+    // staged elements of this thread: e = tid and tid + 256 (kFnNP <= 512);
+    // their mapped columns, and the values of the next plane in registers
+    constexpr int kPer = (kFnNP + 255) / 256;
+    int64_t ecol[kPer];
+    for (int j = 0; j < kPer; ++j) {
+      const int e = min(tid + 256 * j, kFnNP - 1);
+      const int xe = xp0 - 2 + e % kFnPX, ye = yp0 - 2 + e / kFnPX;  // fine coordinates
+      ecol[j] = fine_at(b, map_axis(xe, fx, b.wall[0]), map_axis(ye, fy, b.wall[1]), 0);
+    }
+    const int64_t fplane = static_cast<int64_t>(fx) * fy;
+    TP next[kPer];
+    auto load = [&](int q) {  // padded plane q: fine plane q - 1, continued
+      const int64_t zoff = map_axis(q - 1, fz, b.wall[2]) * fplane;
+      for (int j = 0; j < kPer; ++j) next[j] = fphi[ecol[j] + zoff];
+    };
+    auto commit = [&]() {
+      for (int j = 0; j < kPer; ++j)
+        if (tid + 256 * j < kFnNP) sP[tid + 256 * j] = dec<double>(next[j], 0.f, 1.f);
+    };
+    // filtered values of the staged plane at this thread's column (as
+    // diag_filter): F[0] = s_x s_y phi, F[1] = s_y d_x phi, F[2] = s_x d_y phi,
+    // F[3] = phi, s = (1, 4, 1), d = (-1, 0, 1)
+    auto filt = [&](double F[4]) {
+      const int c0 = (ly + 1) * kFnPX + lx + 1;
+      double sx[3], dx[3];
+      for (int cy = 0; cy < 3; ++cy) {
+        const int e = c0 + (cy - 1) * kFnPX;
+        const double l = sP[e - 1], c = sP[e], h = sP[e + 1];
+        sx[cy] = l + 4.0 * c + h;
+        dx[cy] = h - l;
+      }
+      F[0] = sx[0] + 4.0 * sx[1] + sx[2];
+      F[1] = dx[0] + 4.0 * dx[1] + dx[2];
+      F[2] = sx[2] - sx[0];
+      F[3] = sP[c0];
+    };
+    double F[3][4] = {};
+    double Bm[3] = {}, B0[3] = {}, Bp[3] = {};  // coarse planes c - 1, c, c + 1 of the mirror plane
+    int cur = -3;
+    load(zp0 - 1);
+    for (int q = zp0 - 1; q <= zp1; ++q) {
+      commit();
+      __syncthreads();
+      if (q < zp1) load(q + 1);  // in flight while this plane is filtered and used
       for (int k = 0; k < 4; ++k) {
         F[0][k] = F[1][k];
         F[1][k] = F[2][k];
+      }
+      filt(F[2]);
+      __syncthreads();
+      if (q < zp0 + 1 || !active) continue;  // output padded plane q - 1 needs planes q - 2 .. q
+      const int Zp = q - 1;
+      int kzs;
+      const int zm = map_axis(Zp - 1, fz, b.wall[2], kzs);
+      const int c = zm >> 1;
+      if (c != cur) {
+        if (c == cur + 1) {
+          for (int a = 0; a < 3; ++a) {
+            Bm[a] = B0[a];
+            B0[a] = Bp[a];
+          }
+          coarse_plane(c + 1, Bp);
+        } else {
+          coarse_plane(c - 1, Bm);
+          coarse_plane(c, B0);
+          coarse_plane(c + 1, Bp);
+        }
+        cur = c;
+      }
+      const double* Bn = (zm & 1) ? Bp : Bm;
+      const double su = ((kxs + kys + kzs) & 1) ? -1.0 : 1.0;
+      const double phi = F[1][3];
+      const double g[3] = {(F[0][1] + 4.0 * F[1][1] + F[2][1]) * (kInvH / 72.0),
+                           (F[0][2] + 4.0 * F[1][2] + F[2][2]) * (kInvH / 72.0), (F[2][0] - F[0][0]) * (kInvH / 72.0)};
+      const double inv = rcp_newton(sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + 1e-12);
+      const double pp = phi * (1.0 - phi);
+      for (int a = 0; a < 3; ++a) {
+        const double uf = su * (0.75 * B0[a] + 0.25 * Bn[a]);
+        G[fgrid_at(b, a, Xp, Yp, Zp)] = Enc<TP>::go(phi * uf + kac * (pp * g[a] * inv), 0.f, 1.f);
       }
     }
   }
 }
 
-// phi_f' = phi_f - div_h G + M lap_h phi_f.  A unit marches one fine column
-// over up to kHoZ planes with the filtered planes z-1, z, z+1 of phi and of G
-// (read from the padded grid, no ghost logic) in registers.
+// phi_f' = phi_f - div_h G + M lap_h phi_f.  A workgroup of 256 threads
+// owns a tile of kFnTX x kFnTY fine columns and marches it over up to kHoZ
+// planes.  Per plane it stages phi and the three components of G with a
+// one-column halo in LDS (G from the padded grid, which already holds the
+// ghost fluxes; phi mirrored or wrapped), each thread filters its column in
+// x and y from LDS, and the filtered values of planes z-1, z, z+1 stay in
+// registers.
+__host__ __device__ inline int fine_phase_tiles(int nx, int ny, int nz) {
+  return ((2 * nx + kFnTX - 1) / kFnTX) * ((2 * ny + kFnTY - 1) / kFnTY) * ((2 * nz + kHoZ - 1) / kHoZ);
+}
+
 template <class PR>
 __global__ void __launch_bounds__(256) fine_phase_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
   using TP = typename PR::TP;
+  __shared__ double sG[3][kFnNP];
+  __shared__ double sP[kFnNP];
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   const int fx = 2 * b.nx, fy = 2 * b.ny, fz = 2 * b.nz;
-  const int64_t ncol = static_cast<int64_t>(fx) * fy;
-  const int64_t units = ncol * ((fz + kHoZ - 1) / kHoZ);
+  const int ntx = (fx + kFnTX - 1) / kFnTX, nty = (fy + kFnTY - 1) / kFnTY;
+  const int tiles = ntx * nty * ((fz + kHoZ - 1) / kHoZ);
   const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
   const gptr<TP> fout = (gptr<TP>)b.fphi[1 - parity];
-  const double* __restrict__ G = b.fgrid;
+  const gptr<const TP> G = (gptr<const TP>)b.fgrid;
   const double mob = b.mobility;
   constexpr double kInvH = 2.0, kInvH2 = 4.0;
-  for (int64_t un = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; un < units;
-       un += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t col = un % ncol;
-    const int X = static_cast<int>(col % fx), Y = static_cast<int>(col / fx);
-    const int z0 = static_cast<int>(un / ncol) * kHoZ, z1 = min(z0 + kHoZ, fz);
-    int xs[3], ys[3];
-    for (int c = -1; c <= 1; ++c) {
-      xs[c + 1] = map_axis(X + c, fx, b.wall[0]);
-      ys[c + 1] = map_axis(Y + c, fy, b.wall[1]);
+  const int tid = threadIdx.x;
+  const int lx = tid % kFnTX, ly = tid / kFnTX;
+  for (int t = blockIdx.x; t < tiles; t += gridDim.x) {  // uniform over the workgroup
+    const int x0 = (t % ntx) * kFnTX, y0 = ((t / ntx) % nty) * kFnTY, z0 = (t / (ntx * nty)) * kHoZ;
+    const int z1 = min(z0 + kHoZ, fz);
+    const int X = x0 + lx, Y = y0 + ly;
+    const bool active = X < fx && Y < fy;
+    // staged elements of this thread (e = tid, tid + 256): mapped phi column,
+    // padded flux column, and the values of the next plane in registers
+    constexpr int kPer = (kFnNP + 255) / 256;
+    int64_t ecol[kPer], gcol[kPer];
+    for (int j = 0; j < kPer; ++j) {
+      const int e = min(tid + 256 * j, kFnNP - 1);
+      const int xe = x0 - 1 + e % kFnPX, ye = y0 - 1 + e / kFnPX;
+      ecol[j] = fine_at(b, map_axis(xe, fx, b.wall[0]), map_axis(ye, fy, b.wall[1]), 0);
+      // padded coordinates; columns past the last tile's edge are never used
+      gcol[j] = fgrid_at(b, 0, min(xe + 1, fx + 1), min(ye + 1, fy + 1), 0);
     }
-    // filtered values of plane q: v[0] = sum w cx Gx, v[1] = sum w cy Gy,
-    // v[2] = sum w Gz, v[3] = sum w phi (w = (1, 4, 1) x (1, 4, 1)), v[4] = phi
-    auto plane = [&](int q, double v[5]) {
-      const int zq = map_axis(q, fz, b.wall[2]);
+    const int64_t fplane = static_cast<int64_t>(fx) * fy;
+    const int64_t gplane = static_cast<int64_t>(fx + 2) * (fy + 2), gcomp = gplane * (fz + 2);
+    TP nP[kPer], nG[3][kPer];
+    auto load = [&](int q) {
+      const int64_t zoff = map_axis(q, fz, b.wall[2]) * fplane, goff = (q + 1) * gplane;
+      for (int j = 0; j < kPer; ++j) {
+        nP[j] = fphi[ecol[j] + zoff];
+        for (int a = 0; a < 3; ++a) nG[a][j] = G[gcol[j] + a * gcomp + goff];
+      }
+    };
+    auto commit = [&]() {
+      for (int j = 0; j < kPer; ++j) {
+        const int e = tid + 256 * j;
+        if (e >= kFnNP) continue;
+        sP[e] = dec<double>(nP[j], 0.f, 1.f);
+        for (int a = 0; a < 3; ++a) sG[a][e] = dec<double>(nG[a][j], 0.f, 1.f);
+      }
+    };
+    // filtered values of the staged plane at this thread's column:
+    // v[0] = sum w cx Gx, v[1] = sum w cy Gy, v[2] = sum w Gz, v[3] = sum w phi
+    // (w = (1, 4, 1) x (1, 4, 1)), v[4] = phi at the column
+    auto filt = [&](double v[5]) {
+      const int c0 = (ly + 1) * kFnPX + lx + 1;
       double hx = 0, hy = 0, hz = 0, L = 0;
       for (int cy = -1; cy <= 1; ++cy)
         for (int cx = -1; cx <= 1; ++cx) {
           const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0);
-          const double ph = dec<double>(fphi[fine_at(b, xs[cx + 1], ys[cy + 1], zq)], 0.f, 1.f);
-          L += w * ph;
-          if (cx == 0 && cy == 0) v[4] = ph;
-          const int xp = X + 1 + cx, yp = Y + 1 + cy, zp = q + 1;
-          if (cx) hx += w * cx * G[fgrid_at(b, 0, xp, yp, zp)];
-          if (cy) hy += w * cy * G[fgrid_at(b, 1, xp, yp, zp)];
-          hz += w * G[fgrid_at(b, 2, xp, yp, zp)];
+          const int e = c0 + cy * kFnPX + cx;
+          if (cx) hx += w * cx * sG[0][e];
+          if (cy) hy += w * cy * sG[1][e];
+          hz += w * sG[2][e];
+          L += w * sP[e];
         }
       v[0] = hx;
       v[1] = hy;
       v[2] = hz;
       v[3] = L;
+      v[4] = sP[c0];
     };
-    double V[3][5];
-    plane(z0 - 1, V[0]);
-    plane(z0, V[1]);
-    for (int z = z0; z < z1; ++z) {
-      plane(z + 1, V[2]);
+    double V[3][5] = {};
+    load(z0 - 1);
+    for (int q = z0 - 1; q <= z1; ++q) {
+      commit();
+      __syncthreads();
+      if (q < z1) load(q + 1);  // in flight while this plane is filtered and used
+      for (int k = 0; k < 5; ++k) {
+        V[0][k] = V[1][k];
+        V[1][k] = V[2][k];
+      }
+      filt(V[2]);
+      __syncthreads();
+      if (q < z0 + 1 || !active) continue;  // output plane q - 1 needs planes q - 2 .. q
+      const int z = q - 1;
       const double phi = V[1][4];
       const double div = ((V[0][0] + 4.0 * V[1][0] + V[2][0]) + (V[0][1] + 4.0 * V[1][1] + V[2][1]) +
                           (V[2][2] - V[0][2])) * (kInvH / 72.0);
       const double lap = ((V[0][3] + 4.0 * V[1][3] + V[2][3]) * (1.0 / 36.0) - 6.0 * phi) * kInvH2;
       fout[fine_at(b, X, Y, z)] = Enc<TP>::go(phi - div + mob * lap, 0.f, 1.f);
-      for (int k = 0; k < 5; ++k) {
-        V[0][k] = V[1][k];
-        V[1][k] = V[2][k];
-      }
     }
   }
 }
@@ -1124,15 +1220,6 @@ hipError_t launch_high_order_phase(int precision, bool gc, bool literal, const B
   });
 }
 
-int fine_blocks_per_box(int64_t max_units) {
-  const int64_t nb = (max_units + 255) / 256;
-  return static_cast<int>(nb < 1 ? 1 : (nb > 8192 ? 8192 : nb));
-}
-
-int64_t fine_units(int nx, int ny, int nz) {
-  return std::max(fine_flux_units(nx, ny, nz), fine_phase_units(nx, ny, nz));
-}
-
 hipError_t launch_fine_init(int precision, const BoxDesc& box, const BoxDesc* d_box, int parity, hipStream_t stream) {
   const int64_t nf = 8 * static_cast<int64_t>(box.nx) * box.ny * box.nz;
   const int64_t n = nf / 8;
@@ -1169,9 +1256,14 @@ hipError_t launch_fine_get(int precision, const BoxDesc& box, int parity, double
   });
 }
 
+int fine_tiles(int nx, int ny, int nz, bool flux) {
+  return flux ? fine_flux_tiles(nx, ny, nz) : fine_phase_tiles(nx, ny, nz);
+}
+
 hipError_t launch_fine_phase(int precision, bool gc, const BoxDesc* d_boxes, int box0, int nbox, int parity,
-                             int u_blocks, int fine_blocks, int restrict_blocks, hipStream_t stream) {
-  if (nbox <= 0 || u_blocks <= 0 || fine_blocks <= 0 || restrict_blocks <= 0) return hipErrorInvalidValue;
+                             int u_blocks, int flux_tiles, int phase_tiles, int restrict_blocks, hipStream_t stream) {
+  if (nbox <= 0 || u_blocks <= 0 || flux_tiles <= 0 || phase_tiles <= 0 || restrict_blocks <= 0)
+    return hipErrorInvalidValue;
   return dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
     if (gc)
@@ -1182,9 +1274,9 @@ hipError_t launch_fine_phase(int precision, bool gc, const BoxDesc* d_boxes, int
                          parity);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fine_flux_kernel<PR>), dim3(fine_blocks, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    hipLaunchKernelGGL((fine_flux_kernel<PR>), dim3(flux_tiles, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((fine_phase_kernel<PR>), dim3(fine_blocks, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    hipLaunchKernelGGL((fine_phase_kernel<PR>), dim3(phase_tiles, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((fine_restrict_kernel<PR>), dim3(restrict_blocks, nbox), dim3(256), 0, stream, d_boxes, box0,
                        1 - parity);

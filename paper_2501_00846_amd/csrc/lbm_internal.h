@@ -90,13 +90,12 @@ hipError_t launch_fine_get(int precision, const BoxDesc& box, int parity, double
 // - 1: reads level `parity` (coarse state and fine phi), writes the fine phi
 // of buffer 1 - parity and overwrites the coarse phi of buffer 1 - parity
 // with its restriction.  Runs after the fused step of the same parity.
-// u_blocks: high_order_blocks_per_box of the largest box; fine_blocks:
-// fine_blocks_per_box of the largest fine_units; restrict_blocks: workgroups
-// per box of the restriction.
+// u_blocks: high_order_blocks_per_box of the largest box; flux_tiles /
+// phase_tiles: the largest fine_tiles(..., true / false) over the boxes (one
+// workgroup per tile); restrict_blocks: workgroups per box of the restriction.
 hipError_t launch_fine_phase(int precision, bool gc, const BoxDesc* d_boxes, int box0, int nbox, int parity,
-                             int u_blocks, int fine_blocks, int restrict_blocks, hipStream_t stream);
-int64_t fine_units(int nx, int ny, int nz);
-int fine_blocks_per_box(int64_t max_units);
+                             int u_blocks, int flux_tiles, int phase_tiles, int restrict_blocks, hipStream_t stream);
+int fine_tiles(int nx, int ny, int nz, bool flux);
 
 constexpr int kDiagValues = 28;
 constexpr int kDiagBlocks = 1024;

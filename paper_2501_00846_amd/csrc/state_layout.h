@@ -44,10 +44,11 @@ struct BoxDesc {
                           // LBM_FINE_PHASE: 3 such planes (u); else NULL
   // LBM_FINE_PHASE: the phase field on the grid refined by 2 per axis,
   // [2nz][2ny][2nx] (compact) of the phi storage type, per parity; and the
-  // fine flux of the step, 3 planes [3][2nz+2][2ny+2][2nx+2] of doubles over
-  // the fine grid grown by one ghost layer on every side.  NULL otherwise.
+  // fine flux of the step, 3 planes [3][2nz+2][2ny+2][2nx+2] of the phi
+  // storage type over the fine grid grown by one ghost layer on every side.
+  // NULL otherwise.
   void* fphi[2];
-  double* fgrid;
+  void* fgrid;
 };
 
 // One unit of work of the fused step: an output tile (x0, y0) of one box,
