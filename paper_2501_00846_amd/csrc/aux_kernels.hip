@@ -890,10 +890,17 @@ __global__ void fine_decode_kernel(BoxDesc b, int s, double* __restrict__ dst, i
 // beyond a wall, wrapped on a periodic axis) in LDS; each thread filters its
 // column in x and y and keeps the filtered planes z-1, z, z+1 in registers.
 // On the continued field the gradient at a ghost node is the mirror node's
-// with the crossed components negated, as the ghost rule asks; the velocity
-// there is the interpolation at the mirror node, negated per crossed wall.
+// with the crossed components negated, as the ghost rule asks.
+// The velocity is the trilinear interpolation of the coarse u continued
+// across the boundary as an odd field (minus the mirror value beyond a
+// wall), which at a ghost node equals minus the interpolation at its mirror
+// node.  Each coarse plane the tile needs is staged in LDS once (its region:
+// kFnUX x kFnUY coarse columns), loaded one fine plane ahead of its first
+// use; every thread keeps the x-y bilinear sums of coarse planes c - 1, c,
+// c + 1 around its fine plane in registers.
 constexpr int kFnTX = 32, kFnTY = 8;
 constexpr int kFnPX = kFnTX + 2, kFnPY = kFnTY + 2, kFnNP = kFnPX * kFnPY;
+constexpr int kFnUX = kFnTX / 2 + 4, kFnUY = kFnTY / 2 + 3, kFnUN = kFnUX * kFnUY;
 
 __host__ __device__ inline int fine_flux_tiles(int nx, int ny, int nz) {
   return ((2 * nx + 2 + kFnTX - 1) / kFnTX) * ((2 * ny + 2 + kFnTY - 1) / kFnTY) * ((2 * nz + 2 + kHoZ - 1) / kHoZ);
@@ -903,6 +910,7 @@ template <class PR>
 __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
   using TP = typename PR::TP;
   __shared__ double sP[kFnNP];
+  __shared__ double sU[3][kFnUN];
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   const int nx = b.nx, ny = b.ny;
   const int fx = 2 * nx, fy = 2 * ny, fz = 2 * b.nz;
@@ -910,6 +918,7 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
   const int ntx = (px + kFnTX - 1) / kFnTX, nty = (py + kFnTY - 1) / kFnTY;
   const int tiles = ntx * nty * ((pz + kHoZ - 1) / kHoZ);
   const int64_t n = static_cast<int64_t>(nx) * ny * b.nz;
+  const int64_t cplane = static_cast<int64_t>(nx) * ny;
   const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
   const double* __restrict__ u = b.aux;
   const gptr<TP> G = (gptr<TP>)b.fgrid;
@@ -917,42 +926,14 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
   constexpr double kInvH = 2.0;  // 1 / h
   const int tid = threadIdx.x;
   const int lx = tid % kFnTX, ly = tid / kFnTX;
+  constexpr int kPer = (kFnNP + 255) / 256;
+  constexpr int kPerU = (3 * kFnUN + 255) / 256;
   for (int t = blockIdx.x; t < tiles; t += gridDim.x) {  // uniform over the workgroup
     const int xp0 = (t % ntx) * kFnTX, yp0 = ((t / ntx) % nty) * kFnTY, zp0 = (t / (ntx * nty)) * kHoZ;
     const int zp1 = min(zp0 + kHoZ, pz);
     const int Xp = xp0 + lx, Yp = yp0 + ly;
     const bool active = Xp < px && Yp < py;
-    // the mirror (or periodic image) column of this padded column
-    int kxs, kys;
-    const int xm = map_axis(Xp - 1, fx, b.wall[0], kxs);
-    const int ym = map_axis(Yp - 1, fy, b.wall[1], kys);
-    // the trilinear interpolation of u at the mirror column, split as the x-y
-    // (bilinear) sum over its four coarse neighbours per coarse plane -- each
-    // coarse plane summed once per march and used by the fine planes around
-    // it -- then 3/4 and 1/4 along z.  A coarse ghost beyond a wall is minus
-    // its mirror node.
-    int ux[2], uy[2], ukx[2] = {0, 0}, uky[2] = {0, 0};
-    ux[0] = xm >> 1;
-    uy[0] = ym >> 1;
-    ux[1] = map_axis(ux[0] + ((xm & 1) ? 1 : -1), nx, b.wall[0], ukx[1]);
-    uy[1] = map_axis(uy[0] + ((ym & 1) ? 1 : -1), ny, b.wall[1], uky[1]);
-    auto coarse_plane = [&](int p, double B[3]) {
-      int kz;
-      const int pm = map_axis(p, b.nz, b.wall[2], kz);
-      for (int a = 0; a < 3; ++a) {
-        double acc = 0.0;
-        for (int dy = 0; dy < 2; ++dy)
-          for (int dx = 0; dx < 2; ++dx) {
-            const double w = (dx ? 0.25 : 0.75) * (dy ? 0.25 : 0.75);
-            const double v = u[a * n + (static_cast<int64_t>(pm) * ny + uy[dy]) * nx + ux[dx]];
-            acc += ((ukx[dx] + uky[dy] + kz) & 1) ? -w * v : w * v;
-          }
-        B[a] = acc;
-      }
-    };
-    // staged elements of this thread: e = tid and tid + 256 (kFnNP <= 512);
-    // their mapped columns, and the values of the next plane in registers
-    constexpr int kPer = (kFnNP + 255) / 256;
+    // phi staging: this thread's elements (e = tid, tid + 256), mapped columns
     int64_t ecol[kPer];
     for (int j = 0; j < kPer; ++j) {
       const int e = min(tid + 256 * j, kFnNP - 1);
@@ -969,7 +950,47 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
       for (int j = 0; j < kPer; ++j)
         if (tid + 256 * j < kFnNP) sP[tid + 256 * j] = dec<double>(next[j], 0.f, 1.f);
     };
-    // filtered values of the staged plane at this thread's column (as
+    // velocity staging: region of unmapped coarse columns [cx0, cx0 + kFnUX) x
+    // [cy0, cy0 + kFnUY) around the tile; this thread's elements, their
+    // physical columns and the signs of the odd continuation in x and y
+    const int cx0 = ((xp0 - 1) >> 1) - 1, cy0 = ((yp0 - 1) >> 1) - 1;
+    int64_t ucol[kPerU];
+    bool uneg[kPerU];
+    for (int j = 0; j < kPerU; ++j) {
+      const int e = min(tid + 256 * j, 3 * kFnUN - 1);
+      const int a = e / kFnUN, r = e % kFnUN;
+      int kx, ky;
+      const int cx = map_axis(cx0 + r % kFnUX, nx, b.wall[0], kx);
+      const int cy = map_axis(cy0 + r / kFnUX, ny, b.wall[1], ky);
+      ucol[j] = a * n + static_cast<int64_t>(cy) * nx + cx;
+      uneg[j] = ((kx + ky) & 1) != 0;
+    }
+    double unext[kPerU];
+    auto load_u = [&](int p) {  // unmapped coarse plane p
+      int kz;
+      const int64_t zoff = map_axis(p, b.nz, b.wall[2], kz) * cplane;
+      for (int j = 0; j < kPerU; ++j) {
+        const double v = u[ucol[j] + zoff];
+        unext[j] = (uneg[j] != (kz != 0)) ? -v : v;
+      }
+    };
+    auto commit_u = [&]() {
+      for (int j = 0; j < kPerU; ++j) {
+        const int e = tid + 256 * j;
+        if (e < 3 * kFnUN) sU[e / kFnUN][e % kFnUN] = unext[j];
+      }
+    };
+    // this thread's fine node (unmapped X = Xp - 1): coarse cell X >> 1 with
+    // weight 3/4, its neighbour towards the node with weight 1/4
+    const int X = Xp - 1, Y = Yp - 1;
+    const int li = (X >> 1) - cx0, lj = (Y >> 1) - cy0;
+    const int lni = li + ((X & 1) ? 1 : -1), lnj = lj + ((Y & 1) ? 1 : -1);
+    auto bilinear = [&](double B[3]) {
+      for (int a = 0; a < 3; ++a)
+        B[a] = 0.75 * (0.75 * sU[a][lj * kFnUX + li] + 0.25 * sU[a][lj * kFnUX + lni]) +
+               0.25 * (0.75 * sU[a][lnj * kFnUX + li] + 0.25 * sU[a][lnj * kFnUX + lni]);
+    };
+    // filtered values of the staged phi plane at this thread's column (as
     // diag_filter): F[0] = s_x s_y phi, F[1] = s_y d_x phi, F[2] = s_x d_y phi,
     // F[3] = phi, s = (1, 4, 1), d = (-1, 0, 1)
     auto filt = [&](double F[4]) {
@@ -986,12 +1007,26 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
       F[2] = sx[2] - sx[0];
       F[3] = sP[c0];
     };
+    // bilinear sums of the coarse planes around the first output plane
+    // (unmapped fine plane Z0 = zp0 - 1, coarse plane c0 = Z0 >> 1)
+    double Bm[3], B0[3], Bp[3];
+    {
+      const int c0 = (zp0 - 1) >> 1;
+      double* Bs[3] = {Bm, B0, Bp};
+      for (int k = 0; k < 3; ++k) {
+        load_u(c0 - 1 + k);
+        commit_u();
+        __syncthreads();
+        bilinear(Bs[k]);
+        __syncthreads();
+      }
+    }
+    bool u_pending = false;
     double F[3][4] = {};
-    double Bm[3] = {}, B0[3] = {}, Bp[3] = {};  // coarse planes c - 1, c, c + 1 of the mirror plane
-    int cur = -3;
     load(zp0 - 1);
     for (int q = zp0 - 1; q <= zp1; ++q) {
       commit();
+      if (u_pending) commit_u();
       __syncthreads();
       if (q < zp1) load(q + 1);  // in flight while this plane is filtered and used
       for (int k = 0; k < 4; ++k) {
@@ -999,35 +1034,34 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
         F[1][k] = F[2][k];
       }
       filt(F[2]);
+      double Bnew[3];
+      const bool fresh = u_pending;
+      if (fresh) bilinear(Bnew);
+      u_pending = false;
       __syncthreads();
-      if (q < zp0 + 1 || !active) continue;  // output padded plane q - 1 needs planes q - 2 .. q
-      const int Zp = q - 1;
-      int kzs;
-      const int zm = map_axis(Zp - 1, fz, b.wall[2], kzs);
-      const int c = zm >> 1;
-      if (c != cur) {
-        if (c == cur + 1) {
-          for (int a = 0; a < 3; ++a) {
-            Bm[a] = B0[a];
-            B0[a] = Bp[a];
-          }
-          coarse_plane(c + 1, Bp);
-        } else {
-          coarse_plane(c - 1, Bm);
-          coarse_plane(c, B0);
-          coarse_plane(c + 1, Bp);
+      if (q < zp0 + 1) continue;  // output padded plane q - 1 needs planes q - 2 .. q
+      const int Zp = q - 1, Z = Zp - 1;  // unmapped fine plane
+      const int c = Z >> 1;
+      if (fresh) {  // c advanced: planes c - 1, c, c + 1
+        for (int a = 0; a < 3; ++a) {
+          Bm[a] = B0[a];
+          B0[a] = Bp[a];
+          Bp[a] = Bnew[a];
         }
-        cur = c;
       }
-      const double* Bn = (zm & 1) ? Bp : Bm;
-      const double su = ((kxs + kys + kzs) & 1) ? -1.0 : 1.0;
+      if ((Z & 1) && Zp + 1 < zp1) {  // the next output plane starts coarse plane c + 1
+        load_u(c + 2);
+        u_pending = true;
+      }
+      if (!active) continue;
+      const double* Bn = (Z & 1) ? Bp : Bm;
       const double phi = F[1][3];
       const double g[3] = {(F[0][1] + 4.0 * F[1][1] + F[2][1]) * (kInvH / 72.0),
                            (F[0][2] + 4.0 * F[1][2] + F[2][2]) * (kInvH / 72.0), (F[2][0] - F[0][0]) * (kInvH / 72.0)};
       const double inv = rcp_newton(sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + 1e-12);
       const double pp = phi * (1.0 - phi);
       for (int a = 0; a < 3; ++a) {
-        const double uf = su * (0.75 * B0[a] + 0.25 * Bn[a]);
+        const double uf = 0.75 * B0[a] + 0.25 * Bn[a];
         G[fgrid_at(b, a, Xp, Yp, Zp)] = Enc<TP>::go(phi * uf + kac * (pp * g[a] * inv), 0.f, 1.f);
       }
     }
