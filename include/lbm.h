@@ -106,7 +106,8 @@ enum {
    * lbm_set_state is carried to the fine grid by the same interpolation and
    * the coarse phi becomes its restriction; lbm_get_fine_phase /
    * lbm_set_fine_phase read and write the fine field itself.  The diffusive
-   * part is stable for 4 * mobility below about 0.35.  Each box keeps two
+   * part of the fine FTCS update is stable for mobility <= 0.0865 (larger
+   * values are rejected with LBM_ERR_ARG).  Each box keeps two
    * fine phi buffers (8 N values of the phi storage type each), the flux of a
    * step (3 (2nx+2)(2ny+2)(2nz+2) values of that type) and the coarse
    * velocity (3 N doubles); a step runs four more kernels.  All boxes of a context must

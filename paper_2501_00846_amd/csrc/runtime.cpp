@@ -129,6 +129,10 @@ lbm_status validate_box(const lbm_params& p, int idx, int precision0, const char
   if (p.flags & ~(LBM_LITERAL_ADVECTION | LBM_GRADIENT_CLOSURE | LBM_HIGH_ORDER_AC | LBM_FINE_PHASE)) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: unknown flags 0x%x", who, idx, p.flags);
   if ((p.flags & LBM_FINE_PHASE) && (p.flags & (LBM_HIGH_ORDER_AC | LBM_LITERAL_ADVECTION)))
     return fail(nullptr, LBM_ERR_UNSUPPORTED, "%s: box %d: LBM_FINE_PHASE is not combined with LBM_HIGH_ORDER_AC or LBM_LITERAL_ADVECTION", who, idx);
+  // FTCS diffusion on the fine grid (spacing 1/2): stable while 4 M |l_min| <= 2,
+  // l_min = -5.78 the most negative symbol of the isotropic Laplacian
+  if ((p.flags & LBM_FINE_PHASE) && finite(p.mobility) && p.mobility > 2.0 / (4.0 * 5.78))
+    return fail(nullptr, LBM_ERR_ARG, "%s: box %d: mobility %g too large for LBM_FINE_PHASE (stable FTCS diffusion on the fine grid needs mobility <= 0.0865)", who, idx, p.mobility);
   if (p.flags & LBM_HIGH_ORDER_AC)
     for (int a = 0; a < 3; ++a)
       if (p.bc[a] == LBM_WALL && d[a] < 4) return fail(nullptr, LBM_ERR_ARG, "%s: box %d: wall axis %d needs >= 4 nodes with LBM_HIGH_ORDER_AC", who, idx, a);

@@ -200,3 +200,7 @@ def test_fine_phase_variant_checks():
     assert st == -2 and "LBM_FINE_PHASE" in msg
     st, msg = _noalloc(_params(flags=8))
     assert st == -2 and "LBM_FINE_PHASE" in msg
+    p = _params(flags=8)
+    p.mobility = 0.09  # 4 M * 5.78 > 2: the fine grid's FTCS diffusion would be unstable
+    st, _, msg = _create([p])
+    assert st == -1 and "mobility" in msg
