@@ -781,9 +781,8 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
 //   ho_flux_kernel<PR, GC, false>  coarse u = J + a/2 into b.aux;
 //   fine_flux_kernel   G = phi u_f + (4M/W) phi (1 - phi) n over the fine grid
 //                      grown by one ghost layer (b.fgrid, in the phi storage
-//                      type), u_f the trilinear
-//                      interpolation of the coarse u, n from the isotropic
-//                      gradient at spacing h;
+//                      type), u_f the trilinear interpolation of the coarse
+//                      u, n from the isotropic gradient at spacing h;
 //   fine_phase_kernel  phi_f' = phi_f - div_h G + M lap_h phi_f into the other
 //                      fine buffer (the isotropic stencils of Sec. II.C
 //                      divided by h and h^2);
@@ -804,27 +803,24 @@ __device__ __forceinline__ int64_t fgrid_at(const BoxDesc& b, int a, int xp, int
 }
 
 // Trilinear interpolation at fine node (X, Y, Z) of a coarse field read by
-// ld(x, y, z) at mapped coordinates: per axis coarse node X >> 1 with weight
-// 3/4 and its neighbour towards the fine node (X even: below, odd: above)
-// with weight 1/4.  ODD: a coarse ghost beyond a wall is minus the mirrored
-// value (velocity); otherwise the mirrored value.
-template <bool ODD, class Load>
+// ld(x, y, z) at mapped coordinates (a coarse ghost beyond a wall takes the
+// mirrored value): per axis coarse node X >> 1 with weight 3/4 and its
+// neighbour towards the fine node (X even: below, odd: above) with weight 1/4.
+template <class Load>
 __device__ __forceinline__ double interp_fine(const BoxDesc& b, int X, int Y, int Z, const Load& ld) {
-  int cx[2], cy[2], cz[2], kx[2] = {0, 0}, ky[2] = {0, 0}, kz[2] = {0, 0};
+  int cx[2], cy[2], cz[2];
   cx[0] = X >> 1;
   cy[0] = Y >> 1;
   cz[0] = Z >> 1;
-  cx[1] = map_axis(cx[0] + ((X & 1) ? 1 : -1), b.nx, b.wall[0], kx[1]);
-  cy[1] = map_axis(cy[0] + ((Y & 1) ? 1 : -1), b.ny, b.wall[1], ky[1]);
-  cz[1] = map_axis(cz[0] + ((Z & 1) ? 1 : -1), b.nz, b.wall[2], kz[1]);
+  cx[1] = map_axis(cx[0] + ((X & 1) ? 1 : -1), b.nx, b.wall[0]);
+  cy[1] = map_axis(cy[0] + ((Y & 1) ? 1 : -1), b.ny, b.wall[1]);
+  cz[1] = map_axis(cz[0] + ((Z & 1) ? 1 : -1), b.nz, b.wall[2]);
   double s = 0.0;
   for (int dz = 0; dz < 2; ++dz)
     for (int dy = 0; dy < 2; ++dy)
       for (int dx = 0; dx < 2; ++dx) {
         const double w = (dx ? 0.25 : 0.75) * (dy ? 0.25 : 0.75) * (dz ? 0.25 : 0.75);
-        double v = ld(cx[dx], cy[dy], cz[dz]);
-        if (ODD && ((kx[dx] + ky[dy] + kz[dz]) & 1)) v = -v;
-        s += w * v;
+        s += w * ld(cx[dx], cy[dy], cz[dz]);
       }
   return s;
 }
@@ -841,7 +837,7 @@ __global__ void fine_prolong_kernel(BoxDesc b, int s) {
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int X = static_cast<int>(i % fx), Y = static_cast<int>((i / fx) % fy), Z = static_cast<int>(i / fx / fy);
     auto ld = [&](int x, int y, int z) { return dec<double>(cphi[phi_at(b, x, y, z)], 0.f, 1.f); };
-    fphi[i] = Enc<TP>::go(interp_fine<false>(b, X, Y, Z, ld), 0.f, 1.f);
+    fphi[i] = Enc<TP>::go(interp_fine(b, X, Y, Z, ld), 0.f, 1.f);
   }
 }
 

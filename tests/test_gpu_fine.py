@@ -198,3 +198,40 @@ def test_ensemble_one_launch_equals_separate_boxes():
         alone = _gpu(p, states[i], fines[i], 3)
         assert np.array_equal(together[i][0], alone[0]), i
         assert np.array_equal(together[i][1], alone[1]), i
+
+
+@pytest.mark.parametrize("precision", ["fp16_os", "bf16_os"])
+def test_one_step_16_bit_storage(precision):
+    """16-bit moment storage (the phase fields in FP32): one step matches the
+    oracle run from the host-quantised inputs within the storage modes'
+    tolerance, the fine phase field within FP32 rounding."""
+    prob = _prob((17, 9, 7), (W_, W_, W_), rho_g=1e-3, nu_l=1 / 60, nu_g=1 / 6,
+                 gravity=(0.0, 0.0, -1e-5), rho_ref=1.0)
+    state = quantize_state(smooth_random_state(prob, seed=33), precision)
+    phif = _fine_field(prob, seed=34).astype(np.float32).astype(np.float64)
+    got, gotf = _gpu(prob, state, phif, 1, precision)
+    ref, reff = _oracle(prob, state, phif, 1)
+    tol = field_tolerance(precision, ref)
+    for k, name in enumerate(FIELDS):
+        worst = float((np.abs(got[k] - ref[k]) / tol[k]).max())
+        assert worst <= 1.0, (name, worst)
+    assert _fine_err(gotf, reff) <= 2e-5
+
+
+def test_unbatched_steps_equal_batched_steps():
+    """One launch per box per step gives bitwise the batched launch's result."""
+    probs = [_prob((12, 10, 9), (P_, P_, P_)), _prob((19, 15, 12), (P_, W_, W_))]
+    states = [smooth_random_state(p, seed=80 + i) for i, p in enumerate(probs)]
+    out = []
+    for unbatched in (False, True):
+        with lbm.Context(probs, "fp64") as ctx:
+            for i, s in enumerate(states):
+                ctx.set_state(i, s.reshape(-1))
+            if unbatched:
+                ctx.step_unbatched(3)
+            else:
+                ctx.step(3)
+            out.append([(ctx.get_state(i), ctx.get_fine_phase(i)) for i in range(2)])
+    for i in range(2):
+        assert np.array_equal(out[0][i][0], out[1][i][0]), i
+        assert np.array_equal(out[0][i][1], out[1][i][1]), i
