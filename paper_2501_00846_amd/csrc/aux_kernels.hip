@@ -905,8 +905,9 @@ __host__ __device__ inline int fine_flux_tiles(int nx, int ny, int nz) {
 template <class PR>
 __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
   using TP = typename PR::TP;
-  __shared__ double sP[kFnNP];
-  __shared__ double sU[3][kFnUN];
+  using RA = TP;  // arithmetic: FP64 for FP64 storage, FP32 otherwise
+  __shared__ RA sP[kFnNP];
+  __shared__ RA sU[3][kFnUN];
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   const int nx = b.nx, ny = b.ny;
   const int fx = 2 * nx, fy = 2 * ny, fz = 2 * b.nz;
@@ -918,8 +919,8 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
   const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
   const double* __restrict__ u = b.aux;
   const gptr<TP> G = (gptr<TP>)b.fgrid;
-  const double kac = b.kappa_ac;
-  constexpr double kInvH = 2.0;  // 1 / h
+  const RA kac = static_cast<RA>(b.kappa_ac);
+  constexpr RA kInvH = 2;  // 1 / h
   const int tid = threadIdx.x;
   const int lx = tid % kFnTX, ly = tid / kFnTX;
   constexpr int kPer = (kFnNP + 255) / 256;
@@ -944,7 +945,7 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
     };
     auto commit = [&]() {
       for (int j = 0; j < kPer; ++j)
-        if (tid + 256 * j < kFnNP) sP[tid + 256 * j] = dec<double>(next[j], 0.f, 1.f);
+        if (tid + 256 * j < kFnNP) sP[tid + 256 * j] = dec<RA>(next[j], 0.f, 1.f);
     };
     // velocity staging: region of unmapped coarse columns [cx0, cx0 + kFnUX) x
     // [cy0, cy0 + kFnUY) around the tile; this thread's elements, their
@@ -961,12 +962,12 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
       ucol[j] = a * n + static_cast<int64_t>(cy) * nx + cx;
       uneg[j] = ((kx + ky) & 1) != 0;
     }
-    double unext[kPerU];
+    RA unext[kPerU];
     auto load_u = [&](int p) {  // unmapped coarse plane p
       int kz;
       const int64_t zoff = map_axis(p, b.nz, b.wall[2], kz) * cplane;
       for (int j = 0; j < kPerU; ++j) {
-        const double v = u[ucol[j] + zoff];
+        const RA v = static_cast<RA>(u[ucol[j] + zoff]);
         unext[j] = (uneg[j] != (kz != 0)) ? -v : v;
       }
     };
@@ -981,34 +982,34 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
     const int X = Xp - 1, Y = Yp - 1;
     const int li = (X >> 1) - cx0, lj = (Y >> 1) - cy0;
     const int lni = li + ((X & 1) ? 1 : -1), lnj = lj + ((Y & 1) ? 1 : -1);
-    auto bilinear = [&](double B[3]) {
+    auto bilinear = [&](RA B[3]) {
       for (int a = 0; a < 3; ++a)
-        B[a] = 0.75 * (0.75 * sU[a][lj * kFnUX + li] + 0.25 * sU[a][lj * kFnUX + lni]) +
-               0.25 * (0.75 * sU[a][lnj * kFnUX + li] + 0.25 * sU[a][lnj * kFnUX + lni]);
+        B[a] = RA(0.75) * (RA(0.75) * sU[a][lj * kFnUX + li] + RA(0.25) * sU[a][lj * kFnUX + lni]) +
+               RA(0.25) * (RA(0.75) * sU[a][lnj * kFnUX + li] + RA(0.25) * sU[a][lnj * kFnUX + lni]);
     };
     // filtered values of the staged phi plane at this thread's column (as
     // diag_filter): F[0] = s_x s_y phi, F[1] = s_y d_x phi, F[2] = s_x d_y phi,
     // F[3] = phi, s = (1, 4, 1), d = (-1, 0, 1)
-    auto filt = [&](double F[4]) {
+    auto filt = [&](RA F[4]) {
       const int c0 = (ly + 1) * kFnPX + lx + 1;
-      double sx[3], dx[3];
+      RA sx[3], dx[3];
       for (int cy = 0; cy < 3; ++cy) {
         const int e = c0 + (cy - 1) * kFnPX;
-        const double l = sP[e - 1], c = sP[e], h = sP[e + 1];
-        sx[cy] = l + 4.0 * c + h;
+        const RA l = sP[e - 1], c = sP[e], h = sP[e + 1];
+        sx[cy] = l + RA(4) * c + h;
         dx[cy] = h - l;
       }
-      F[0] = sx[0] + 4.0 * sx[1] + sx[2];
-      F[1] = dx[0] + 4.0 * dx[1] + dx[2];
+      F[0] = sx[0] + RA(4) * sx[1] + sx[2];
+      F[1] = dx[0] + RA(4) * dx[1] + dx[2];
       F[2] = sx[2] - sx[0];
       F[3] = sP[c0];
     };
     // bilinear sums of the coarse planes around the first output plane
     // (unmapped fine plane Z0 = zp0 - 1, coarse plane c0 = Z0 >> 1)
-    double Bm[3], B0[3], Bp[3];
+    RA Bm[3], B0[3], Bp[3];
     {
       const int c0 = (zp0 - 1) >> 1;
-      double* Bs[3] = {Bm, B0, Bp};
+      RA* Bs[3] = {Bm, B0, Bp};
       for (int k = 0; k < 3; ++k) {
         load_u(c0 - 1 + k);
         commit_u();
@@ -1018,7 +1019,7 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
       }
     }
     bool u_pending = false;
-    double F[3][4] = {};
+    RA F[3][4] = {};
     load(zp0 - 1);
     for (int q = zp0 - 1; q <= zp1; ++q) {
       commit();
@@ -1030,7 +1031,7 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
         F[1][k] = F[2][k];
       }
       filt(F[2]);
-      double Bnew[3];
+      RA Bnew[3];
       const bool fresh = u_pending;
       if (fresh) bilinear(Bnew);
       u_pending = false;
@@ -1050,14 +1051,14 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
         u_pending = true;
       }
       if (!active) continue;
-      const double* Bn = (Z & 1) ? Bp : Bm;
-      const double phi = F[1][3];
-      const double g[3] = {(F[0][1] + 4.0 * F[1][1] + F[2][1]) * (kInvH / 72.0),
-                           (F[0][2] + 4.0 * F[1][2] + F[2][2]) * (kInvH / 72.0), (F[2][0] - F[0][0]) * (kInvH / 72.0)};
-      const double inv = rcp_newton(sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + 1e-12);
-      const double pp = phi * (1.0 - phi);
+      const RA* Bn = (Z & 1) ? Bp : Bm;
+      const RA phi = F[1][3];
+      const RA g[3] = {(F[0][1] + RA(4) * F[1][1] + F[2][1]) * (kInvH / RA(72)),
+                       (F[0][2] + RA(4) * F[1][2] + F[2][2]) * (kInvH / RA(72)), (F[2][0] - F[0][0]) * (kInvH / RA(72))};
+      const RA inv = rcp_newton(sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + RA(1e-12));
+      const RA pp = phi * (RA(1) - phi);
       for (int a = 0; a < 3; ++a) {
-        const double uf = 0.75 * B0[a] + 0.25 * Bn[a];
+        const RA uf = RA(0.75) * B0[a] + RA(0.25) * Bn[a];
         G[fgrid_at(b, a, Xp, Yp, Zp)] = Enc<TP>::go(phi * uf + kac * (pp * g[a] * inv), 0.f, 1.f);
       }
     }
@@ -1078,8 +1079,9 @@ __host__ __device__ inline int fine_phase_tiles(int nx, int ny, int nz) {
 template <class PR>
 __global__ void __launch_bounds__(256) fine_phase_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
   using TP = typename PR::TP;
-  __shared__ double sG[3][kFnNP];
-  __shared__ double sP[kFnNP];
+  using RA = TP;  // arithmetic: FP64 for FP64 storage, FP32 otherwise
+  __shared__ RA sG[3][kFnNP];
+  __shared__ RA sP[kFnNP];
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   const int fx = 2 * b.nx, fy = 2 * b.ny, fz = 2 * b.nz;
   const int ntx = (fx + kFnTX - 1) / kFnTX, nty = (fy + kFnTY - 1) / kFnTY;
@@ -1087,8 +1089,8 @@ __global__ void __launch_bounds__(256) fine_phase_kernel(const BoxDesc* __restri
   const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
   const gptr<TP> fout = (gptr<TP>)b.fphi[1 - parity];
   const gptr<const TP> G = (gptr<const TP>)b.fgrid;
-  const double mob = b.mobility;
-  constexpr double kInvH = 2.0, kInvH2 = 4.0;
+  const RA mob = static_cast<RA>(b.mobility);
+  constexpr RA kInvH = 2, kInvH2 = 4;
   const int tid = threadIdx.x;
   const int lx = tid % kFnTX, ly = tid / kFnTX;
   for (int t = blockIdx.x; t < tiles; t += gridDim.x) {  // uniform over the workgroup
@@ -1121,22 +1123,22 @@ __global__ void __launch_bounds__(256) fine_phase_kernel(const BoxDesc* __restri
       for (int j = 0; j < kPer; ++j) {
         const int e = tid + 256 * j;
         if (e >= kFnNP) continue;
-        sP[e] = dec<double>(nP[j], 0.f, 1.f);
-        for (int a = 0; a < 3; ++a) sG[a][e] = dec<double>(nG[a][j], 0.f, 1.f);
+        sP[e] = dec<RA>(nP[j], 0.f, 1.f);
+        for (int a = 0; a < 3; ++a) sG[a][e] = dec<RA>(nG[a][j], 0.f, 1.f);
       }
     };
     // filtered values of the staged plane at this thread's column:
     // v[0] = sum w cx Gx, v[1] = sum w cy Gy, v[2] = sum w Gz, v[3] = sum w phi
     // (w = (1, 4, 1) x (1, 4, 1)), v[4] = phi at the column
-    auto filt = [&](double v[5]) {
+    auto filt = [&](RA v[5]) {
       const int c0 = (ly + 1) * kFnPX + lx + 1;
-      double hx = 0, hy = 0, hz = 0, L = 0;
+      RA hx = 0, hy = 0, hz = 0, L = 0;
       for (int cy = -1; cy <= 1; ++cy)
         for (int cx = -1; cx <= 1; ++cx) {
-          const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0);
+          const RA w = (cx ? RA(1) : RA(4)) * (cy ? RA(1) : RA(4));
           const int e = c0 + cy * kFnPX + cx;
-          if (cx) hx += w * cx * sG[0][e];
-          if (cy) hy += w * cy * sG[1][e];
+          if (cx) hx += w * RA(cx) * sG[0][e];
+          if (cy) hy += w * RA(cy) * sG[1][e];
           hz += w * sG[2][e];
           L += w * sP[e];
         }
@@ -1146,7 +1148,7 @@ __global__ void __launch_bounds__(256) fine_phase_kernel(const BoxDesc* __restri
       v[3] = L;
       v[4] = sP[c0];
     };
-    double V[3][5] = {};
+    RA V[3][5] = {};
     load(z0 - 1);
     for (int q = z0 - 1; q <= z1; ++q) {
       commit();
@@ -1160,10 +1162,10 @@ __global__ void __launch_bounds__(256) fine_phase_kernel(const BoxDesc* __restri
       __syncthreads();
       if (q < z0 + 1 || !active) continue;  // output plane q - 1 needs planes q - 2 .. q
       const int z = q - 1;
-      const double phi = V[1][4];
-      const double div = ((V[0][0] + 4.0 * V[1][0] + V[2][0]) + (V[0][1] + 4.0 * V[1][1] + V[2][1]) +
-                          (V[2][2] - V[0][2])) * (kInvH / 72.0);
-      const double lap = ((V[0][3] + 4.0 * V[1][3] + V[2][3]) * (1.0 / 36.0) - 6.0 * phi) * kInvH2;
+      const RA phi = V[1][4];
+      const RA div = ((V[0][0] + RA(4) * V[1][0] + V[2][0]) + (V[0][1] + RA(4) * V[1][1] + V[2][1]) +
+                      (V[2][2] - V[0][2])) * (kInvH / RA(72));
+      const RA lap = ((V[0][3] + RA(4) * V[1][3] + V[2][3]) * RA(1.0 / 36.0) - RA(6) * phi) * kInvH2;
       fout[fine_at(b, X, Y, z)] = Enc<TP>::go(phi - div + mob * lap, 0.f, 1.f);
     }
   }
