@@ -91,9 +91,10 @@ enum {
    * isotropic D3Q27 stencil at spacings 1 and 2 (the higher-order
    * discretisation named as future work at the end of Sec. II.A; the flow
    * solver keeps the second-order stencils of Sec. II.C).  Wall axes need
-   * at least 4 nodes.  Each step then also keeps 6 doubles per node of
-   * device memory (velocity and sharpening flux of level n) and runs two
-   * more kernels.  All boxes of a context must agree on this flag and, with
+   * at least 4 nodes.  Each step then also keeps 6 values per node of
+   * device memory in the phi storage type (velocity and sharpening flux of
+   * level n), runs two more kernels, and computes the phase update in the
+   * precision of the stored phi.  All boxes of a context must agree on this flag and, with
    * it, on LBM_LITERAL_ADVECTION; not available through lbm_step_noalloc. */
   LBM_HIGH_ORDER_AC = 4,
   /* Finer phase-field grid (the finer grid named as future work at the end
@@ -110,8 +111,8 @@ enum {
    * values are rejected with LBM_ERR_ARG).  Each box keeps two
    * fine phi buffers (8 N values of the phi storage type each), the flux of a
    * step (3 (2nx+2)(2ny+2)(2nz+2) values of that type) and the coarse
-   * velocity (3 N doubles); a step runs four more kernels.  All boxes of a context must
-   * agree on this flag; not combined with LBM_HIGH_ORDER_AC or
+   * velocity (3 N values of that type); a step runs four more kernels.  All
+   * boxes of a context must agree on this flag; not combined with LBM_HIGH_ORDER_AC or
    * LBM_LITERAL_ADVECTION, and not available through lbm_step_noalloc. */
   LBM_FINE_PHASE = 8
 };

@@ -464,9 +464,10 @@ __global__ void __launch_bounds__(kDiagThreads) diag_final_kernel(const double* 
 // its phi output is overwritten).  Two kernels, both reading level n:
 //   ho_flux_kernel  per node: u = J + a/2 with the forces of Sec. II.C (in
 //                   FP64, as the diagnostics compute it) and S = phi (1 - phi)
-//                   n4, n4 the unit fourth-order gradient; 6 doubles into
-//                   b.aux;
-//   ho_phase_kernel per node: phi' = phi - div4(phi u) + M lap4(phi)
+//                   n4, n4 the unit fourth-order gradient; 6 values in the
+//                   phi storage type into b.aux;
+//   ho_phase_kernel per node, in the phi storage type's precision:
+//                   phi' = phi - div4(phi u) + M lap4(phi)
 //                   - (4M/W) div4(S), or u . grad4(phi) for the printed
 //                   advection.  Neighbours beyond a wall are mirrored nodes,
 //                   with u negated per crossed wall and the crossed
@@ -478,8 +479,9 @@ __global__ void __launch_bounds__(kDiagThreads) diag_final_kernel(const double* 
 
 constexpr int kHoZ = 64;  // planes per work unit / tile of the z-marches
 
-// u and S = phi (1 - phi) n4 per node into b.aux (6 compact planes; with
-// WS false u only, 3 planes, for the finer phase grid).  Work units: one
+// u and S = phi (1 - phi) n4 per node into b.aux (6 compact planes in the
+// phi storage type; with WS false u only, 3 planes, for the finer phase
+// grid).  Work units: one
 // column (x, y) over up to kHoZ planes, consecutive threads on consecutive x.
 // Per plane the thread filters phi over its 3 x 3 columns at spacing 1 (F1)
 // and at spacing 2 (F2), the raw values of the next planes and the node's
@@ -495,7 +497,7 @@ __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict_
   const int64_t units = ncol * ((nz + kHoZ - 1) / kHoZ);
   const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
   const gptr<const TM> fmom = (gptr<const TM>)b.mom[parity];
-  double* __restrict__ aux = b.aux;
+  TP* __restrict__ aux = reinterpret_cast<TP*>(b.aux);
   constexpr int NMOM = GC ? 4 : 10;
   for (int64_t un = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; un < units;
        un += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -609,8 +611,8 @@ __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict_
         for (int c = 0; c < 3; ++c) qg += Q[a][c] * g[c] * b.drho;
         const double F = mu * g[a] - P * (1.0 / 3.0) * b.drho * g[a] - 3.0 * nu * om * qg +
                          (rho - b.rho_ref) * b.grav[a];
-        aux[a * n + i] = m[1 + a] + 0.5 * F / rho;
-        if constexpr (WS) aux[(3 + a) * n + i] = pp * g4[a] * inv;
+        aux[a * n + i] = static_cast<TP>(m[1 + a] + 0.5 * F / rho);
+        if constexpr (WS) aux[(3 + a) * n + i] = static_cast<TP>(pp * g4[a] * inv);
       }
       for (int k = 0; k < 4; ++k) {
         F1[0][k] = F1[1][k];
@@ -644,9 +646,10 @@ constexpr int kHoPer = (kHoNP + 255) / 256;  // staged elements per thread
 template <class PR, bool LIT>
 __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
   using TP = typename PR::TP;
+  using RA = TP;  // arithmetic: FP64 for FP64 storage, FP32 otherwise
   constexpr int NV = LIT ? 6 : 4;  // filtered values per plane
-  __shared__ double sG[3][kHoNP];
-  __shared__ double sP[kHoNP];
+  __shared__ RA sG[3][kHoNP];
+  __shared__ RA sP[kHoNP];
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   const int nx = b.nx, ny = b.ny, nz = b.nz;
   const int ntx = (nx + kHoTX - 1) / kHoTX, nty = (ny + kHoTY - 1) / kHoTY;
@@ -656,9 +659,9 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
   const int x0 = (t % ntx) * kHoTX, y0 = ((t / ntx) % nty) * kHoTY, z0 = (t / (ntx * nty)) * kHoZ;
   const int z1 = min(z0 + kHoZ, nz);
   const int64_t n = static_cast<int64_t>(nx) * ny * nz;
-  const double* __restrict__ aux = b.aux;
+  const TP* __restrict__ aux = reinterpret_cast<const TP*>(b.aux);
   const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
-  const double kac = b.kappa_ac, mob = b.mobility;
+  const RA kac = static_cast<RA>(b.kappa_ac), mob = static_cast<RA>(b.mobility);
   const int tid = threadIdx.x;
   const int lx = tid % kHoTX, ly = tid / kHoTX;
   const int x = x0 + lx, y = y0 + ly;
@@ -672,18 +675,33 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
     ey[j] = map_axis(y0 - 2 + ee / kHoPX, ny, b.wall[1], eky[j]);
     ecol[j] = ey[j] * nx + ex[j];
   }
-  auto stage = [&](int q) {
-    int kz;
-    const int zq = map_axis(q, nz, b.wall[2], kz);
+  // the next plane's staged values, loaded into registers a plane ahead:
+  // raw phi, u and S of each element, and the plane's z crossing
+  TP nph[kHoPer];
+  TP nu[kHoPer][3], ns[kHoPer][3];
+  int nkz = 0;
+  auto load = [&](int q) {
+    const int zq = map_axis(q, nz, b.wall[2], nkz);
+    for (int j = 0; j < kHoPer; ++j) {  // elements past kHoNP load element 0 (never committed)
+      const int64_t i = static_cast<int64_t>(zq) * nx * ny + ecol[j];
+      nph[j] = fphi[phi_at(b, ex[j], ey[j], zq)];
+      for (int a = 0; a < 3; ++a) {
+        if constexpr (!LIT) nu[j][a] = aux[a * n + i];
+        ns[j][a] = aux[(3 + a) * n + i];
+      }
+    }
+  };
+  auto commit = [&]() {
     for (int j = 0; j < kHoPer; ++j) {
       const int e = tid + 256 * j;
       if (e >= kHoNP) continue;
-      const int64_t i = static_cast<int64_t>(zq) * nx * ny + ecol[j];
-      const double ph = dec<double>(fphi[phi_at(b, ex[j], ey[j], zq)], 0.f, 1.f);
-      const double su = ((ekx[j] + eky[j] + kz) & 1) ? -1.0 : 1.0;
-      const double r[3] = {ekx[j] ? -1.0 : 1.0, eky[j] ? -1.0 : 1.0, kz ? -1.0 : 1.0};
-      const double pa = LIT ? 0.0 : su * ph;
-      for (int a = 0; a < 3; ++a) sG[a][e] = pa * aux[a * n + i] + kac * (r[a] * aux[(3 + a) * n + i]);
+      const RA ph = dec<RA>(nph[j], 0.f, 1.f);
+      const RA su = ((ekx[j] + eky[j] + nkz) & 1) ? RA(-1) : RA(1);
+      const RA r[3] = {ekx[j] ? RA(-1) : RA(1), eky[j] ? RA(-1) : RA(1), nkz ? RA(-1) : RA(1)};
+      for (int a = 0; a < 3; ++a) {
+        const RA adv = LIT ? RA(0) : su * ph * nu[j][a];
+        sG[a][e] = adv + kac * (r[a] * ns[j][a]);
+      }
       sP[e] = ph;
     }
   };
@@ -691,12 +709,12 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
   // v[0] = sum_cy w(cy) (Gx(+s, cy) - Gx(-s, cy)), v[1] likewise for Gy
   // along y, v[2] = sum w w Gz, v[3] = sum w w phi, v[4], v[5] = the
   // x and y differences of phi (printed advection)
-  auto filt = [&](int s, double* v) {
+  auto filt = [&](int s, RA* v) {
     const int c0 = (ly + 2) * kHoPX + lx + 2;
-    double hx = 0, hy = 0, hz = 0, L = 0, dx = 0, dy = 0;
+    RA hx = 0, hy = 0, hz = 0, L = 0, dx = 0, dy = 0;
     for (int cy = -1; cy <= 1; ++cy)
       for (int cx = -1; cx <= 1; ++cx) {
-        const double w = (cx ? 1.0 : 4.0) * (cy ? 1.0 : 4.0);
+        const RA w = RA((cx ? 1 : 4) * (cy ? 1 : 4));
         const int e = c0 + s * (cy * kHoPX + cx);
         hx += w * cx * sG[0][e];
         hy += w * cy * sG[1][e];
@@ -720,16 +738,18 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
   // (index 0 .. 3; z-1, z, z+1 used), V2 at spacing 2 for planes z-2 .. z+2
   // (index 0 .. 4; z-2, z, z+2 used); PC: phi at the column for planes z,
   // z+1, z+2
-  double V1[4][NV], V2[5][NV], PC[3];
+  RA V1[4][NV], V2[5][NV], PC[3];
+  load(z0 - 2);
   for (int q = z0 - 2; q <= z1 + 1; ++q) {
-    stage(q);
+    commit();
     __syncthreads();
+    if (q < z1 + 1) load(q + 1);  // in flight while this plane is filtered and used
     const int k1 = q - (z0 - 2);  // planes staged so far - 1
     {
-      double v1[NV], v2[NV];
+      RA v1[NV], v2[NV];
       filt(1, v1);
       filt(2, v2);
-      const double pc = sP[(ly + 2) * kHoPX + lx + 2];
+      const RA pc = sP[(ly + 2) * kHoPX + lx + 2];
       // shift the rings and append plane q
       for (int k = 0; k < NV; ++k) {
         for (int p = 0; p < 3; ++p) V1[p][k] = V1[p + 1][k];
@@ -745,26 +765,27 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
     if (k1 < 4) continue;  // output plane z = q - 2 needs planes z-2 .. z+2
     const int z = q - 2;
     if (!active) continue;
-    const double phi = PC[0];
-    const double div1 = (V1[0][0] + 4.0 * V1[1][0] + V1[2][0]) + (V1[0][1] + 4.0 * V1[1][1] + V1[2][1]) +
-                        (V1[2][2] - V1[0][2]);
-    const double div2 = (V2[0][0] + 4.0 * V2[2][0] + V2[4][0]) + (V2[0][1] + 4.0 * V2[2][1] + V2[4][1]) +
-                        (V2[4][2] - V2[0][2]);
-    const double lap1 = (V1[0][3] + 4.0 * V1[1][3] + V1[2][3]) * (1.0 / 36.0) - 6.0 * phi;
-    const double lap2 = (V2[0][3] + 4.0 * V2[2][3] + V2[4][3]) * (1.0 / 144.0) - 1.5 * phi;
-    const double div4 = (4.0 * div1 * (1.0 / 72.0) - div2 * (1.0 / 144.0)) / 3.0;
-    const double lap4 = (4.0 * lap1 - lap2) / 3.0;
-    double adv = 0.0;
+    const RA phi = PC[0];
+    const RA div1 = (V1[0][0] + RA(4) * V1[1][0] + V1[2][0]) + (V1[0][1] + RA(4) * V1[1][1] + V1[2][1]) +
+                    (V1[2][2] - V1[0][2]);
+    const RA div2 = (V2[0][0] + RA(4) * V2[2][0] + V2[4][0]) + (V2[0][1] + RA(4) * V2[2][1] + V2[4][1]) +
+                    (V2[4][2] - V2[0][2]);
+    const RA lap1 = (V1[0][3] + RA(4) * V1[1][3] + V1[2][3]) * RA(1.0 / 36.0) - RA(6) * phi;
+    const RA lap2 = (V2[0][3] + RA(4) * V2[2][3] + V2[4][3]) * RA(1.0 / 144.0) - RA(1.5) * phi;
+    const RA div4 = (RA(4) * div1 * RA(1.0 / 72.0) - div2 * RA(1.0 / 144.0)) / RA(3);
+    const RA lap4 = (RA(4) * lap1 - lap2) / RA(3);
+    RA adv = 0;
     if constexpr (LIT) {
       const int64_t i = (static_cast<int64_t>(z) * ny + y) * nx + x;
-      const double g1[3] = {(V1[0][4] + 4.0 * V1[1][4] + V1[2][4]) * (1.0 / 72.0),
-                            (V1[0][5] + 4.0 * V1[1][5] + V1[2][5]) * (1.0 / 72.0), (V1[2][3] - V1[0][3]) * (1.0 / 72.0)};
-      const double g2[3] = {(V2[0][4] + 4.0 * V2[2][4] + V2[4][4]) * (1.0 / 144.0),
-                            (V2[0][5] + 4.0 * V2[2][5] + V2[4][5]) * (1.0 / 144.0),
-                            (V2[4][3] - V2[0][3]) * (1.0 / 144.0)};
-      for (int a = 0; a < 3; ++a) adv += aux[a * n + i] * (4.0 * g1[a] - g2[a]) / 3.0;
+      const RA g1[3] = {(V1[0][4] + RA(4) * V1[1][4] + V1[2][4]) * RA(1.0 / 72.0),
+                        (V1[0][5] + RA(4) * V1[1][5] + V1[2][5]) * RA(1.0 / 72.0),
+                        (V1[2][3] - V1[0][3]) * RA(1.0 / 72.0)};
+      const RA g2[3] = {(V2[0][4] + RA(4) * V2[2][4] + V2[4][4]) * RA(1.0 / 144.0),
+                        (V2[0][5] + RA(4) * V2[2][5] + V2[4][5]) * RA(1.0 / 144.0),
+                        (V2[4][3] - V2[0][3]) * RA(1.0 / 144.0)};
+      for (int a = 0; a < 3; ++a) adv += aux[a * n + i] * (RA(4) * g1[a] - g2[a]) / RA(3);
     }
-    const double phin = phi - adv - div4 + mob * lap4;
+    const RA phin = phi - adv - div4 + mob * lap4;
     ((gptr<TP>)b.phi[1 - parity])[phi_at(b, x, y, z)] = Enc<TP>::go(phin, 0.f, 1.f);
   }
 }
@@ -917,7 +938,7 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
   const int64_t n = static_cast<int64_t>(nx) * ny * b.nz;
   const int64_t cplane = static_cast<int64_t>(nx) * ny;
   const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
-  const double* __restrict__ u = b.aux;
+  const TP* __restrict__ u = reinterpret_cast<const TP*>(b.aux);
   const gptr<TP> G = (gptr<TP>)b.fgrid;
   const RA kac = static_cast<RA>(b.kappa_ac);
   constexpr RA kInvH = 2;  // 1 / h

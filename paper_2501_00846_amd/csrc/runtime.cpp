@@ -31,7 +31,7 @@ struct Box {
   lbm_params prm{};
   BoxDesc desc{};
   void* mem[2] = {nullptr, nullptr};
-  void* aux = nullptr;  // LBM_HIGH_ORDER_AC: 6 planes of n doubles; LBM_FINE_PHASE: 3
+  void* aux = nullptr;  // phi storage type; LBM_HIGH_ORDER_AC: 6 planes of n values; LBM_FINE_PHASE: 3
   void* fmem[2] = {nullptr, nullptr};  // LBM_FINE_PHASE: fine phi per parity
   void* fgrid = nullptr;               // LBM_FINE_PHASE: fine flux (padded grid)
   int64_t n = 0;
@@ -482,7 +482,7 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
         b.desc.mom[s] = static_cast<char*>(b.mem[s]) + pb;
       }
       if (c->ho) {
-        b.aux = dev_alloc(c, align256(static_cast<size_t>(b.n) * 6 * sizeof(double)));
+        b.aux = dev_alloc(c, align256(lbm::phi_bytes(c->precision, 6 * b.n)));
         if (!b.aux) {
           lbm_destroy(c);
           return fail(nullptr, LBM_ERR_OOM, "lbm_create: high-order phase buffer allocation failed (box %d)", i);
@@ -492,7 +492,7 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
       if (c->fine) {
         const int64_t nf = 8 * b.n;
         const int64_t np = static_cast<int64_t>(2 * b.prm.nx + 2) * (2 * b.prm.ny + 2) * (2 * b.prm.nz + 2);
-        b.aux = dev_alloc(c, align256(static_cast<size_t>(b.n) * 3 * sizeof(double)));
+        b.aux = dev_alloc(c, align256(lbm::phi_bytes(c->precision, 3 * b.n)));
         b.fgrid = dev_alloc(c, align256(lbm::phi_bytes(c->precision, 3 * np)));
         for (int s = 0; s < 2; ++s) b.fmem[s] = dev_alloc(c, align256(lbm::phi_bytes(c->precision, nf)));
         if (!b.aux || !b.fgrid || !b.fmem[0] || !b.fmem[1]) {
