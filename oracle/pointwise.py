@@ -11,7 +11,9 @@ time with explicit index arithmetic instead of whole-array rolls and padding:
     get their reflection signs node by node.
 
 The local physics (density, forces, equilibria, regularisation, source) is the
-one of scheme.py, evaluated on single nodes.  Used on tiny grids to check the
+one of scheme.py, evaluated on single nodes.  FinePointOracle does the same for
+the finer phase-field grid (scheme.py F1-F5): the fine FTCS update node by node,
+the coarse u interpolated per fine node, and the restriction per coarse cell.  Used on tiny grids to check the
 streaming and boundary indexing of scheme.py, and on sampled nodes of full-size
 problems where the whole-array oracle does not fit in memory.
 """
@@ -207,6 +209,142 @@ class PointOracle:
         if getattr(prob, "high_order_ac", False):
             phi_new = self.phase_high_order_at(x, y, z)
         return phi_new, P, J, Qn
+
+
+# -- finer phase-field grid (scheme.py F1-F5), node by node --------------------
+def _map_index(periodic, n, i):
+    """Coordinate i of an axis of n nodes mapped into the domain: wrapped if
+    periodic, else mirrored half-way (-1 -> 0).  Returns (index, mirrored)."""
+    if periodic:
+        return i % n, False
+    if i < 0:
+        return -1 - i, True
+    if i >= n:
+        return 2 * n - 1 - i, True
+    return i, False
+
+
+def prolong_at(g_at, prob, X, Y, Z, odd=False):
+    """Trilinear interpolation (F3) of a coarse field at in-domain fine node
+    (X, Y, Z) (F1: fine node I of an axis at I/2 - 1/4): per axis the coarse
+    node I // 2 with weight 3/4 and its neighbour on the fine node's side
+    (I even: below, I odd: above) with weight 1/4.  g_at(x, y, z) reads an
+    in-domain coarse node; a coarse node beyond a wall takes the mirrored
+    node's value, negated per crossed wall when odd."""
+    n = (prob.nx, prob.ny, prob.nz)
+    taps = []
+    for ax, I in enumerate((X, Y, Z)):
+        c = I // 2
+        taps.append(((c, 0.75), (c - 1 if I % 2 == 0 else c + 1, 0.25)))
+    total = 0.0
+    for cx, wx in taps[0]:
+        for cy, wy in taps[1]:
+            for cz, wz in taps[2]:
+                idx, crossed = [], 0
+                for ax, c in enumerate((cx, cy, cz)):
+                    i, m = _map_index(prob.bc[ax] == PERIODIC, n[ax], c)
+                    idx.append(i)
+                    crossed += m
+                v = g_at(*idx)
+                if odd and crossed % 2:
+                    v = -v
+                total = total + (wx * wy * wz) * v
+    return total
+
+
+class FinePointOracle:
+    """One step of scheme.step_fine evaluated at chosen coarse nodes.
+
+    st is the coarse state of level n, whose phi is the restriction of the
+    fine field (F2); phif_at(X, Y, Z) reads the fine phi at an in-domain fine
+    node.  The coarse part of the step (collision, streaming, moments) is
+    PointOracle's; the new coarse phi is the mean of the 8 fine nodes of the
+    cell after the fine FTCS update (F4), whose fluxes use the interpolated
+    coarse u of level n (F3) and, beyond a wall, the mirrored fine node with u
+    negated per crossed wall and the gradient taken on the mirrored field
+    (F5)."""
+
+    def __init__(self, st, phif_at, prob):
+        self.coarse = PointOracle(st, prob)
+        self.phif_at = phif_at
+        self.prob = prob
+        self.nf = (2 * prob.nx, 2 * prob.ny, 2 * prob.nz)
+        self._cache = {}
+
+    def _map(self, ax, i):
+        return _map_index(self.prob.bc[ax] == PERIODIC, self.nf[ax], i)
+
+    def phi_at(self, X, Y, Z):
+        """Fine phi at a fine node that may be a ghost (mirrored value)."""
+        return self.phif_at(self._map(0, X)[0], self._map(1, Y)[0], self._map(2, Z)[0])
+
+    def u_at(self, X, Y, Z):
+        """Interpolated coarse u at an in-domain fine node (F3)."""
+        key = ("u", X, Y, Z)
+        if key not in self._cache:
+            self._cache[key] = prolong_at(lambda x, y, z: self.coarse.node(x, y, z)["u"], self.prob,
+                                          X, Y, Z, odd=True)
+        return self._cache[key]
+
+    def grad_at(self, X, Y, Z):
+        """Isotropic gradient of the fine phi at spacing h (Sec. II.C stencil
+        divided by h) at a fine node that may be a ghost."""
+        key = ("g", X, Y, Z)
+        if key not in self._cache:
+            g = np.zeros(3)
+            for i in range(NQ):
+                cx, cy, cz = (int(v) for v in C[i])
+                g += (W[i] / CS2) * self.phi_at(X + cx, Y + cy, Z + cz) * C[i]
+            self._cache[key] = g / scheme.FINE_H
+        return self._cache[key]
+
+    def flux_parts(self, X, Y, Z):
+        """(phi, u, n) at a fine node that may be a ghost (F5)."""
+        idx, crossed = [], 0
+        for ax, I in enumerate((X, Y, Z)):
+            i, m = self._map(ax, I)
+            idx.append(i)
+            crossed += m
+        u = self.u_at(*idx) * (-1.0) ** crossed
+        g = self.grad_at(X, Y, Z)
+        n = g / (np.sqrt(np.sum(g ** 2)) + scheme.EPS_NORMAL)
+        return self.phif_at(*idx), u, n
+
+    def phase_at(self, X, Y, Z):
+        """phi_f' at an in-domain fine node: the FTCS update of Sec. II.D with
+        the divergence divided by h and the Laplacian by h^2 (F4)."""
+        prob, h = self.prob, scheme.FINE_H
+        kac = 4.0 * prob.mobility / prob.width
+        ph0 = self.phif_at(X, Y, Z)
+        adv = sharp = lap = 0.0
+        for i in range(NQ):
+            cx, cy, cz = (int(v) for v in C[i])
+            ph, u, n = self.flux_parts(X + cx, Y + cy, Z + cz)
+            adv += (W[i] / CS2) * ph * float(np.dot(u, C[i]))
+            sharp += (W[i] / CS2) * ph * (1.0 - ph) * float(np.dot(n, C[i]))
+            lap += (2.0 * W[i] / CS2) * (ph - ph0)
+        return ph0 - adv / h + prob.mobility * lap / (h * h) - kac * sharp / h
+
+    def step_at(self, x, y, z):
+        """(phi', P', J'(3), Q'(3x3)) at in-domain coarse node (x, y, z);
+        phi' is the restriction of the 8 updated fine nodes (F2)."""
+        _, P, J, Qn = self.coarse.step_at(x, y, z)
+        kids = [self.phase_at(2 * x + dx, 2 * y + dy, 2 * z + dz)
+                for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]
+        return float(np.mean(kids)), P, J, Qn
+
+
+def step_points_fine(st, phif_at, prob, points):
+    """step_points for the finer phase grid (FinePointOracle)."""
+    po = FinePointOracle(st, phif_at, prob)
+    out = dict(phi=[], P=[], J=[], Q=[])
+    for (x, y, z) in points:
+        phi, P, J, Qn = po.step_at(int(x), int(y), int(z))
+        out["phi"].append(phi)
+        out["P"].append(P)
+        out["J"].append(J)
+        out["Q"].append(Qn)
+    return {k: np.array(v) for k, v in out.items()}
 
 
 def step_points(st, prob, points):

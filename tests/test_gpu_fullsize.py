@@ -33,7 +33,16 @@ def _reference(case, precision, pts):
 
 
 def _compare(got, refa, precision, force=None):
+    """FP64: 1e-12 of phi's scale for phi and of the population scale
+    max(|P|, |J|, the moment's own) for each moment -- a moment is a signed
+    sum of populations of that size, so its FP64 rounding is relative to it
+    (a small off-diagonal Q at sampled nodes carries the rounding of sums of
+    O(|P|) terms).  Reduced precision: field_tolerance."""
     tols = field_tolerance(precision, refa, force=force)
+    if precision == "fp64":
+        s_mom = max(np.abs(refa[1]).max(), np.abs(refa[2:5]).max())
+        for k in range(1, 11):
+            tols[k] = 1e-12 * max(np.abs(refa[k]).max(), s_mom) + 1e-300
     for k, name in enumerate(FIELDS):
         scale = np.abs(refa[k]).max()
         tol = tols[k]
@@ -255,3 +264,76 @@ def test_rising_bubble_128x128x256_100_steps_fp64():
         err = np.abs(v - np.array(gold["observables"][name])).max() / gold["max_abs"][name]
         _log("  %-4s max err / field scale %.3e" % (name, err))
         assert err <= 1e-10, name
+
+
+POOL_EXTRA = [(256, 256, 127), (256, 256, 128), (256, 256, 220), (256, 256, 300), (0, 0, 511), (511, 511, 0)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_drop_into_pool_512_high_order_one_step(precision):
+    """The fourth-order phase update on the 512^3 drop into a pool, in both
+    modes the benchmark times: one step at sampled nodes (walls, interface,
+    random) against the per-node oracle's fourth-order stencils."""
+    case = workloads.drop_into_pool()
+    case.problem.high_order_ac = True
+    _check(case, precision, tune=True, extra=POOL_EXTRA)
+
+
+class _Restricted:
+    """Coarse phi as the mean of the 8 fine nodes of each cell, evaluated on
+    demand (optionally rounded to the storage type)."""
+
+    def __init__(self, fine_at, shape, rnd):
+        self.fine_at, self.shape, self.rnd = fine_at, shape, rnd
+        self._cache = {}
+
+    def __getitem__(self, idx):
+        z, y, x = (int(v) for v in idx)
+        if (z, y, x) not in self._cache:
+            kids = [self.fine_at(2 * x + dx, 2 * y + dy, 2 * z + dz)
+                    for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]
+            self._cache[(z, y, x)] = self.rnd(np.mean(kids))
+        return self._cache[(z, y, x)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_drop_into_pool_512_fine_phase_one_step(precision):
+    """The finer phase grid on the 512^3 drop into a pool (1024^3 fine
+    nodes), in both modes the benchmark times: from the seeded initial
+    fields (the fine phi their interpolation, the coarse phi its restriction)
+    one step, checked at sampled coarse nodes against the per-node fine
+    oracle: the flow part, and the new coarse phi, the mean of the 8 updated
+    fine nodes of the cell.  Reduced precision: the fine and coarse phi the
+    oracle starts from are rounded to FP32 like the stored ones."""
+    case = workloads.drop_into_pool()
+    case.problem.fine_phase = True
+    prob = case.problem
+    rng = np.random.default_rng(321)
+    pts = sample_points(prob, rng, n_random=16, extra=POOL_EXTRA)
+    _log("%s fine phase %s: %d sampled nodes" % (case.name, precision, len(pts)))
+    with lbm.Context(prob, precision) as ctx:
+        ctx.init_case(0, case)
+        ctx.autotune(2)
+        ctx.init_case(0, case)
+        _log("tuning %s" % ctx.tuning())
+        ctx.step(1)
+        got = ctx.state_at(0, pts)
+    rnd = (lambda v: float(v)) if precision == "fp64" else (lambda v: float(np.float32(v)))
+    phi0 = quantize(case.phi, precision, 0)
+    cache = {}
+
+    def fine0(X, Y, Z):
+        if (X, Y, Z) not in cache:
+            cache[(X, Y, Z)] = rnd(PW.prolong_at(lambda x, y, z: phi0[z, y, x], prob, X, Y, Z))
+        return cache[(X, Y, Z)]
+
+    q = lambda a, k: None if a is None else quantize(a, precision, k)
+    u = case.u
+    st = LazyState(_Restricted(fine0, prob.shape, rnd), q(case.pstar, 1),
+                   tuple(None if u is None else q(u[a], 2 + a) for a in range(3)))
+    ref = PW.step_points_fine(st, fine0, prob, pts)
+    refa = np.concatenate([ref["phi"][None], ref["P"][None], ref["J"].T,
+                           np.stack([ref["Q"][:, 0, 0], ref["Q"][:, 1, 1], ref["Q"][:, 2, 2],
+                                     ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
+    force = None if precision == "fp64" else force_scale(prob, st.phi, q(case.pstar, 1), pts)
+    _compare(got, refa, precision, force)

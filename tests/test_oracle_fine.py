@@ -12,6 +12,7 @@ l(kh)/h^2 sin(k.x) (Laplacian), h = 1/2, with m(k) = 2/3 + cos(k)/3,
 import numpy as np
 import pytest
 
+from oracle import pointwise as PW
 from oracle import scheme as S
 from paper_2501_00846_amd.workloads import PERIODIC, WALL, Problem
 
@@ -197,3 +198,43 @@ def test_tangential_flow_next_to_a_wall():
     ubar[[1, -2]] = 11 * U / 12
     expect = phif - ubar.reshape(1, 1, 12) * B * np.cos(k * fy) * np.sin(k * H) / H
     assert np.abs(got - expect).max() < 1e-15
+
+
+@pytest.mark.parametrize("bc", [(PERIODIC,) * 3, (WALL,) * 3, (WALL, PERIODIC, WALL)])
+def test_interpolation_node_by_node(bc):
+    """pointwise.prolong_at (one fine node at a time, explicit taps and ghost
+    signs) equals the axis-by-axis whole-array interpolation, even and odd."""
+    prob = Problem(5, 4, 3, bc=bc)
+    g = np.random.default_rng(9).random((3, 4, 5)) - 0.3
+    for odd in (False, True):
+        whole = S.prolong(g, prob, odd=odd)
+        at = lambda x, y, z: g[z, y, x]
+        for Z in range(6):
+            for Y in range(8):
+                for X in range(10):
+                    v = PW.prolong_at(at, prob, X, Y, Z, odd=odd)
+                    assert abs(v - whole[Z, Y, X]) < 1e-15, (odd, X, Y, Z)
+
+
+@pytest.mark.parametrize("bc", [(PERIODIC,) * 3, (WALL,) * 3, (PERIODIC, WALL, WALL)])
+def test_node_by_node_step_equals_whole_array_step(bc):
+    """The per-node form of the fine step (pointwise.FinePointOracle: explicit
+    ghost mapping per fine node, gradient on the mirrored field) equals
+    scheme.step_fine at every coarse node, random smooth state, forces on."""
+    prob = Problem(5, 4, 6, bc=bc, rho_l=1.0, rho_g=0.1, nu_l=0.02, nu_g=0.1, sigma=0.01,
+                   mobility=0.05, width=3.0, gravity=(1e-4, -2e-4, 3e-4), rho_ref=0.5, fine_phase=True)
+    rng = np.random.default_rng(12)
+    phif = 0.5 + 0.4 * np.sin(rng.random((12, 8, 10)) * 3.0)
+    J = 0.02 * (rng.random((3, 6, 4, 5)) - 0.5)
+    st = S.initial_state(S.restrict(phif), u=J)
+    st.P = 0.01 * (rng.random(st.P.shape) - 0.5)
+    st.Q = 1e-3 * (rng.random(st.Q.shape) - 0.5)
+    st.Q = 0.5 * (st.Q + st.Q.transpose(1, 0, 2, 3, 4))
+    ref, _ = S.step_fine(st, phif, prob)
+    pts = [(x, y, z) for z in range(6) for y in range(4) for x in range(5)]
+    got = PW.step_points_fine(st, lambda X, Y, Z: phif[Z, Y, X], prob, pts)
+    for k, (x, y, z) in enumerate(pts):
+        assert abs(got["phi"][k] - ref.phi[z, y, x]) < 1e-14
+        assert abs(got["P"][k] - ref.P[z, y, x]) < 1e-15
+        assert np.abs(got["J"][k] - ref.J[:, z, y, x]).max() < 1e-15
+        assert np.abs(got["Q"][k] - ref.Q[:, :, z, y, x]).max() < 1e-15
