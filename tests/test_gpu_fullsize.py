@@ -75,7 +75,7 @@ def test_rising_bubble_128x128x256_one_step(precision):
     _check(case, precision, extra=extra)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16_os"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16_os", "bf16_os"])
 def test_drop_into_pool_512_one_step(precision):
     case = workloads.drop_into_pool()
     extra = [(256, 256, 127), (256, 256, 128), (256, 256, 220), (256, 256, 300), (0, 0, 511), (511, 511, 0)]
@@ -337,3 +337,21 @@ def test_drop_into_pool_512_fine_phase_one_step(precision):
                                      ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
     force = None if precision == "fp64" else force_scale(prob, st.phi, q(case.pstar, 1), pts)
     _compare(got, refa, precision, force)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16_os"])
+def test_drop_into_pool_512_gradient_closure_one_step(precision):
+    """The gradient closure (state phi, P, J; a2 from the isotropic velocity
+    gradient) on the 512^3 drop into a pool, in the modes it is benchmarked
+    in: one step at sampled nodes against the per-node oracle."""
+    case = workloads.drop_into_pool()
+    case.problem.gradient_closure = True
+    _check(case, precision, tune=True, extra=POOL_EXTRA)
+
+
+def test_rising_bubble_128x128x256_gradient_closure_fp32_one_step():
+    """The gradient closure on the walled 128 x 128 x 256 bubble in FP32 (its
+    FP64 form is in test_gpu_closure.py)."""
+    case = workloads.rising_bubble()
+    case.problem.gradient_closure = True
+    _check(case, "fp32", extra=[(64, 64, 32), (64, 64, 64), (48, 64, 48)])
