@@ -646,7 +646,7 @@ def main():
                  "frac_of_copy": round(m["achieved_gbs"] / copy_gbs, 4),
                  "hbm_floor_ms": round(hbm_floor_ms, 4), "alu": alu,
                  "kernel": "fused_step (%s)" % head + (" + ho_flux + ho_phase" if args.high_order else "") +
-                           (" + ho_flux (u) + fine_flux + fine_phase + fine_restrict" if args.fine_phase else ""),
+                           (" + ho_flux (u) + fine_step + fine_restrict" if args.fine_phase else ""),
                  "kernel_ms": round(m["kernel_ms"], 4),
                  "bytes_per_update": m["bytes_per_update"], "nodes_per_launch": m["nodes"]})
     cpu = None

@@ -109,9 +109,8 @@ enum {
    * lbm_set_fine_phase read and write the fine field itself.  The diffusive
    * part of the fine FTCS update is stable for mobility <= 0.0865 (larger
    * values are rejected with LBM_ERR_ARG).  Each box keeps two
-   * fine phi buffers (8 N values of the phi storage type each), the flux of a
-   * step (3 (2nx+2)(2ny+2)(2nz+2) values of that type) and the coarse
-   * velocity (3 N values of that type); a step runs four more kernels.  All
+   * fine phi buffers (8 N values of the phi storage type each) and the coarse
+   * velocity (3 N values of that type); a step runs three more kernels.  All
    * boxes of a context must agree on this flag; not combined with LBM_HIGH_ORDER_AC or
    * LBM_LITERAL_ADVECTION, and not available through lbm_step_noalloc. */
   LBM_FINE_PHASE = 8

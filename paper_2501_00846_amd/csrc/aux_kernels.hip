@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(256) ho_flux_kernel(const BoxDesc* __restrict_
   const int64_t units = ncol * ((nz + kHoZ - 1) / kHoZ);
   const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
   const gptr<const TM> fmom = (gptr<const TM>)b.mom[parity];
-  TP* __restrict__ aux = reinterpret_cast<TP*>(b.aux);
+  TP* __restrict__ aux = static_cast<TP*>(b.aux);
   constexpr int NMOM = GC ? 4 : 10;
   for (int64_t un = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; un < units;
        un += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -659,7 +659,7 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
   const int x0 = (t % ntx) * kHoTX, y0 = ((t / ntx) % nty) * kHoTY, z0 = (t / (ntx * nty)) * kHoZ;
   const int z1 = min(z0 + kHoZ, nz);
   const int64_t n = static_cast<int64_t>(nx) * ny * nz;
-  const TP* __restrict__ aux = reinterpret_cast<const TP*>(b.aux);
+  const TP* __restrict__ aux = static_cast<const TP*>(b.aux);
   const gptr<const TP> fphi = (gptr<const TP>)b.phi[parity];
   const RA kac = static_cast<RA>(b.kappa_ac), mob = static_cast<RA>(b.mobility);
   const int tid = threadIdx.x;
@@ -800,13 +800,13 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
 // reads the coarse phi, which is kept equal to the mean of the 8 fine nodes
 // of its cell.  After the fused step of a step, reading level n:
 //   ho_flux_kernel<PR, GC, false>  coarse u = J + a/2 into b.aux;
-//   fine_flux_kernel   G = phi u_f + (4M/W) phi (1 - phi) n over the fine grid
-//                      grown by one ghost layer (b.fgrid, in the phi storage
-//                      type), u_f the trilinear interpolation of the coarse
-//                      u, n from the isotropic gradient at spacing h;
-//   fine_phase_kernel  phi_f' = phi_f - div_h G + M lap_h phi_f into the other
+//   fine_step_kernel   phi_f' = phi_f - div_h G + M lap_h phi_f into the other
 //                      fine buffer (the isotropic stencils of Sec. II.C
-//                      divided by h and h^2);
+//                      divided by h and h^2), with the flux
+//                      G = phi u_f + (4M/W) phi (1 - phi) n computed in LDS
+//                      where it is used, u_f the trilinear interpolation of
+//                      the coarse u, n from the isotropic gradient at
+//                      spacing h;
 //   fine_restrict_kernel  coarse phi' = mean of the 8 fine nodes, over the
 //                      fused step's phi output.
 // A ghost node of the fine grid beyond a wall takes the flux of its mirror
@@ -816,11 +816,6 @@ __global__ void __launch_bounds__(256) ho_phase_kernel(const BoxDesc* __restrict
 
 __device__ __forceinline__ int64_t fine_at(const BoxDesc& b, int x, int y, int z) {
   return (static_cast<int64_t>(z) * (2 * b.ny) + y) * (2 * b.nx) + x;
-}
-// component a of the flux at padded fine coordinates (0 and 2n + 1: ghosts)
-__device__ __forceinline__ int64_t fgrid_at(const BoxDesc& b, int a, int xp, int yp, int zp) {
-  const int64_t px = 2 * b.nx + 2, py = 2 * b.ny + 2, pz = 2 * b.nz + 2;
-  return ((a * pz + zp) * py + yp) * px + xp;
 }
 
 // Trilinear interpolation at fine node (X, Y, Z) of a coarse field read by
@@ -900,86 +895,107 @@ __global__ void fine_decode_kernel(BoxDesc b, int s, double* __restrict__ dst, i
     dst[i] = dec<double>(fphi[i], 0.f, 1.f);
 }
 
-// The flux G at every node of the fine grid grown by one ghost layer.  A
-// workgroup of 256 threads owns a tile of kFnTX x kFnTY padded columns and
-// marches it over up to kHoZ padded planes.  Per plane it stages, with a
-// one-column halo, the fine phi continued across the boundary (mirrored
-// beyond a wall, wrapped on a periodic axis) in LDS; each thread filters its
-// column in x and y and keeps the filtered planes z-1, z, z+1 in registers.
-// On the continued field the gradient at a ghost node is the mirror node's
-// with the crossed components negated, as the ghost rule asks.
-// The velocity is the trilinear interpolation of the coarse u continued
-// across the boundary as an odd field (minus the mirror value beyond a
-// wall), which at a ghost node equals minus the interpolation at its mirror
-// node.  Each coarse plane the tile needs is staged in LDS once (its region:
-// kFnUX x kFnUY coarse columns), loaded one fine plane ahead of its first
-// use; every thread keeps the x-y bilinear sums of coarse planes c - 1, c,
-// c + 1 around its fine plane in registers.
-constexpr int kFnTX = 32, kFnTY = 8;
-constexpr int kFnPX = kFnTX + 2, kFnPY = kFnTY + 2, kFnNP = kFnPX * kFnPY;
-constexpr int kFnUX = kFnTX / 2 + 4, kFnUY = kFnTY / 2 + 3, kFnUN = kFnUX * kFnUY;
+// The fine step phi_f' = phi_f - div_h G + M lap_h phi_f, with the flux
+// G = phi u_f + (4M/W) phi (1 - phi) n computed where it is used.  A
+// workgroup of 512 threads owns a tile of kFsTX x kFsTY fine columns and
+// marches it over up to kHoZ planes; each of its first kFsGX x kFsGY threads
+// owns one column of the flux region, the tile grown by one column.  Per
+// staged plane r:
+//   - the fine phi of the tile grown by two columns, continued across the
+//     boundary (mirrored beyond a wall, wrapped on a periodic axis), goes to
+//     LDS; each thread filters its column in x and y and keeps the filtered
+//     planes r-3 .. r in registers;
+//   - each thread computes the flux of plane r-1 at its column into LDS;
+//   - after a barrier the tile's threads filter that flux plane in x and y
+//     and keep the flux planes r-3 .. r-1 in registers, which completes
+//     output plane r-2.
+// On the continued phi field the gradient at a ghost node is the mirror
+// node's with the crossed components negated, as the ghost rule asks.  The
+// velocity is the trilinear interpolation of the coarse u continued as an
+// odd field (minus the mirror value beyond a wall), which at a ghost node
+// equals minus the interpolation at its mirror node.  Each coarse plane the
+// tile needs is staged in LDS once (kFsUX x kFsUY coarse columns), loaded one
+// fine plane ahead of its first use; every thread keeps the x-y bilinear sums
+// of coarse planes c - 1, c, c + 1 around its flux plane in registers.  The
+// staged loads of the next fine plane are issued before the current one is
+// filtered.
+constexpr int kFsThreads = 512;
+constexpr int kFsTX = 32, kFsTY = 13;  // output columns of a tile (kFsTX even)
+constexpr int kFsGX = kFsTX + 2, kFsGY = kFsTY + 2, kFsGN = kFsGX * kFsGY;  // flux region
+constexpr int kFsPX = kFsTX + 4, kFsPY = kFsTY + 4, kFsPN = kFsPX * kFsPY;  // staged phi
+// coarse columns under the flux region: fine X in [x0 - 1, x0 + kFsTX] needs
+// coarse cells (X >> 1) - 1 .. (X >> 1) + 1, at most kFsTX / 2 + 4 of them
+// for even x0, and (kFsTY + 1) / 2 + 3 in y for any y0
+constexpr int kFsUX = kFsTX / 2 + 4, kFsUY = (kFsTY + 1) / 2 + 3, kFsUN = kFsUX * kFsUY;
+static_assert(kFsGN <= kFsThreads, "one flux column per thread");
+static_assert(kFsTX % 2 == 0, "tiles start at even fine x");
 
-__host__ __device__ inline int fine_flux_tiles(int nx, int ny, int nz) {
-  return ((2 * nx + 2 + kFnTX - 1) / kFnTX) * ((2 * ny + 2 + kFnTY - 1) / kFnTY) * ((2 * nz + 2 + kHoZ - 1) / kHoZ);
+__host__ __device__ inline int fine_step_tiles(int nx, int ny, int nz) {
+  return ((2 * nx + kFsTX - 1) / kFsTX) * ((2 * ny + kFsTY - 1) / kFsTY) * ((2 * nz + kHoZ - 1) / kHoZ);
 }
 
 template <class PR>
-__global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
+__global__ void __launch_bounds__(kFsThreads) fine_step_kernel(const BoxDesc* __restrict__ boxes, int box0,
+                                                                  int parity) {
   using TP = typename PR::TP;
   using RA = TP;  // arithmetic: FP64 for FP64 storage, FP32 otherwise
-  __shared__ RA sP[kFnNP];
-  __shared__ RA sU[3][kFnUN];
+  __shared__ RA sP[kFsPN];
+  __shared__ RA sG[3][kFsGN];
+  __shared__ RA sU[3][kFsUN];
   const BoxDesc& b = boxes[box0 + blockIdx.y];
   const int nx = b.nx, ny = b.ny;
   const int fx = 2 * nx, fy = 2 * ny, fz = 2 * b.nz;
-  const int px = fx + 2, py = fy + 2, pz = fz + 2;
-  const int ntx = (px + kFnTX - 1) / kFnTX, nty = (py + kFnTY - 1) / kFnTY;
-  const int tiles = ntx * nty * ((pz + kHoZ - 1) / kHoZ);
+  const int ntx = (fx + kFsTX - 1) / kFsTX, nty = (fy + kFsTY - 1) / kFsTY;
+  const int tiles = ntx * nty * ((fz + kHoZ - 1) / kHoZ);
   const int64_t n = static_cast<int64_t>(nx) * ny * b.nz;
   const int64_t cplane = static_cast<int64_t>(nx) * ny;
+  const int64_t fplane = static_cast<int64_t>(fx) * fy;
   const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
-  const TP* __restrict__ u = reinterpret_cast<const TP*>(b.aux);
-  const gptr<TP> G = (gptr<TP>)b.fgrid;
-  const RA kac = static_cast<RA>(b.kappa_ac);
-  constexpr RA kInvH = 2;  // 1 / h
+  const gptr<TP> fout = (gptr<TP>)b.fphi[1 - parity];
+  const TP* __restrict__ u = static_cast<const TP*>(b.aux);
+  const RA kac = static_cast<RA>(b.kappa_ac), mob = static_cast<RA>(b.mobility);
+  constexpr RA kInvH = 2, kInvH2 = 4;  // 1 / h, 1 / h^2
   const int tid = threadIdx.x;
-  const int lx = tid % kFnTX, ly = tid / kFnTX;
-  constexpr int kPer = (kFnNP + 255) / 256;
-  constexpr int kPerU = (3 * kFnUN + 255) / 256;
+  // this thread's flux column in the region (threads past kFsGN take column
+  // 0 for their reads and store no flux) and whether it is an output column
+  const bool gthread = tid < kFsGN;
+  const int gx = gthread ? tid % kFsGX : 0, gy = gthread ? tid / kFsGX : 0;
+  const bool inner = gthread && gx >= 1 && gx <= kFsTX && gy >= 1 && gy <= kFsTY;
+  constexpr int kPer = (kFsPN + kFsThreads - 1) / kFsThreads;
+  constexpr int kPerU = (3 * kFsUN + kFsThreads - 1) / kFsThreads;
   for (int t = blockIdx.x; t < tiles; t += gridDim.x) {  // uniform over the workgroup
-    const int xp0 = (t % ntx) * kFnTX, yp0 = ((t / ntx) % nty) * kFnTY, zp0 = (t / (ntx * nty)) * kHoZ;
-    const int zp1 = min(zp0 + kHoZ, pz);
-    const int Xp = xp0 + lx, Yp = yp0 + ly;
-    const bool active = Xp < px && Yp < py;
-    // phi staging: this thread's elements (e = tid, tid + 256), mapped columns
+    const int x0 = (t % ntx) * kFsTX, y0 = ((t / ntx) % nty) * kFsTY, z0 = (t / (ntx * nty)) * kHoZ;
+    const int z1 = min(z0 + kHoZ, fz);
+    const int X = x0 - 1 + gx, Y = y0 - 1 + gy;  // unmapped fine column of the flux
+    const bool active = inner && X < fx && Y < fy;
+    // phi staging: this thread's elements, mapped columns (far columns clamp)
     int64_t ecol[kPer];
     for (int j = 0; j < kPer; ++j) {
-      const int e = min(tid + 256 * j, kFnNP - 1);
-      const int xe = xp0 - 2 + e % kFnPX, ye = yp0 - 2 + e / kFnPX;  // fine coordinates
+      const int e = min(tid + kFsThreads * j, kFsPN - 1);
+      const int xe = x0 - 2 + e % kFsPX, ye = y0 - 2 + e / kFsPX;
       ecol[j] = fine_at(b, map_axis(xe, fx, b.wall[0]), map_axis(ye, fy, b.wall[1]), 0);
     }
-    const int64_t fplane = static_cast<int64_t>(fx) * fy;
     TP next[kPer];
-    auto load = [&](int q) {  // padded plane q: fine plane q - 1, continued
-      const int64_t zoff = map_axis(q - 1, fz, b.wall[2]) * fplane;
+    auto load = [&](int r) {  // unmapped fine plane r, continued
+      const int64_t zoff = map_axis(r, fz, b.wall[2]) * fplane;
       for (int j = 0; j < kPer; ++j) next[j] = fphi[ecol[j] + zoff];
     };
     auto commit = [&]() {
       for (int j = 0; j < kPer; ++j)
-        if (tid + 256 * j < kFnNP) sP[tid + 256 * j] = dec<RA>(next[j], 0.f, 1.f);
+        if (tid + kFsThreads * j < kFsPN) sP[tid + kFsThreads * j] = dec<RA>(next[j], 0.f, 1.f);
     };
-    // velocity staging: region of unmapped coarse columns [cx0, cx0 + kFnUX) x
-    // [cy0, cy0 + kFnUY) around the tile; this thread's elements, their
-    // physical columns and the signs of the odd continuation in x and y
-    const int cx0 = ((xp0 - 1) >> 1) - 1, cy0 = ((yp0 - 1) >> 1) - 1;
+    // velocity staging: coarse columns [cx0, cx0 + kFsUX) x [cy0, cy0 + kFsUY),
+    // this thread's elements, their physical columns and the signs of the odd
+    // continuation in x and y
+    const int cx0 = ((x0 - 1) >> 1) - 1, cy0 = ((y0 - 1) >> 1) - 1;
     int64_t ucol[kPerU];
     bool uneg[kPerU];
     for (int j = 0; j < kPerU; ++j) {
-      const int e = min(tid + 256 * j, 3 * kFnUN - 1);
-      const int a = e / kFnUN, r = e % kFnUN;
+      const int e = min(tid + kFsThreads * j, 3 * kFsUN - 1);
+      const int a = e / kFsUN, r = e % kFsUN;
       int kx, ky;
-      const int cx = map_axis(cx0 + r % kFnUX, nx, b.wall[0], kx);
-      const int cy = map_axis(cy0 + r / kFnUX, ny, b.wall[1], ky);
+      const int cx = map_axis(cx0 + r % kFsUX, nx, b.wall[0], kx);
+      const int cy = map_axis(cy0 + r / kFsUX, ny, b.wall[1], ky);
       ucol[j] = a * n + static_cast<int64_t>(cy) * nx + cx;
       uneg[j] = ((kx + ky) & 1) != 0;
     }
@@ -994,28 +1010,27 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
     };
     auto commit_u = [&]() {
       for (int j = 0; j < kPerU; ++j) {
-        const int e = tid + 256 * j;
-        if (e < 3 * kFnUN) sU[e / kFnUN][e % kFnUN] = unext[j];
+        const int e = tid + kFsThreads * j;
+        if (e < 3 * kFsUN) sU[e / kFsUN][e % kFsUN] = unext[j];
       }
     };
-    // this thread's fine node (unmapped X = Xp - 1): coarse cell X >> 1 with
-    // weight 3/4, its neighbour towards the node with weight 1/4
-    const int X = Xp - 1, Y = Yp - 1;
+    // the flux column's coarse cell X >> 1 (weight 3/4) and its neighbour
+    // towards the fine node (weight 1/4), as staged columns
     const int li = (X >> 1) - cx0, lj = (Y >> 1) - cy0;
     const int lni = li + ((X & 1) ? 1 : -1), lnj = lj + ((Y & 1) ? 1 : -1);
     auto bilinear = [&](RA B[3]) {
       for (int a = 0; a < 3; ++a)
-        B[a] = RA(0.75) * (RA(0.75) * sU[a][lj * kFnUX + li] + RA(0.25) * sU[a][lj * kFnUX + lni]) +
-               RA(0.25) * (RA(0.75) * sU[a][lnj * kFnUX + li] + RA(0.25) * sU[a][lnj * kFnUX + lni]);
+        B[a] = RA(0.75) * (RA(0.75) * sU[a][lj * kFsUX + li] + RA(0.25) * sU[a][lj * kFsUX + lni]) +
+               RA(0.25) * (RA(0.75) * sU[a][lnj * kFsUX + li] + RA(0.25) * sU[a][lnj * kFsUX + lni]);
     };
-    // filtered values of the staged phi plane at this thread's column (as
-    // diag_filter): F[0] = s_x s_y phi, F[1] = s_y d_x phi, F[2] = s_x d_y phi,
-    // F[3] = phi, s = (1, 4, 1), d = (-1, 0, 1)
+    // filtered values of the staged phi plane at the flux column:
+    // F[0] = s_x s_y phi, F[1] = s_y d_x phi, F[2] = s_x d_y phi, F[3] = phi,
+    // s = (1, 4, 1), d = (-1, 0, 1)
     auto filt = [&](RA F[4]) {
-      const int c0 = (ly + 1) * kFnPX + lx + 1;
+      const int c0 = (gy + 1) * kFsPX + gx + 1;
       RA sx[3], dx[3];
       for (int cy = 0; cy < 3; ++cy) {
-        const int e = c0 + (cy - 1) * kFnPX;
+        const int e = c0 + (cy - 1) * kFsPX;
         const RA l = sP[e - 1], c = sP[e], h = sP[e + 1];
         sx[cy] = l + RA(4) * c + h;
         dx[cy] = h - l;
@@ -1025,168 +1040,96 @@ __global__ void __launch_bounds__(256) fine_flux_kernel(const BoxDesc* __restric
       F[2] = sx[2] - sx[0];
       F[3] = sP[c0];
     };
-    // bilinear sums of the coarse planes around the first output plane
-    // (unmapped fine plane Z0 = zp0 - 1, coarse plane c0 = Z0 >> 1)
-    RA Bm[3], B0[3], Bp[3];
-    {
-      const int c0 = (zp0 - 1) >> 1;
-      RA* Bs[3] = {Bm, B0, Bp};
-      for (int k = 0; k < 3; ++k) {
-        load_u(c0 - 1 + k);
-        commit_u();
-        __syncthreads();
-        bilinear(Bs[k]);
-        __syncthreads();
-      }
-    }
-    bool u_pending = false;
-    RA F[3][4] = {};
-    load(zp0 - 1);
-    for (int q = zp0 - 1; q <= zp1; ++q) {
-      commit();
-      if (u_pending) commit_u();
-      __syncthreads();
-      if (q < zp1) load(q + 1);  // in flight while this plane is filtered and used
-      for (int k = 0; k < 4; ++k) {
-        F[0][k] = F[1][k];
-        F[1][k] = F[2][k];
-      }
-      filt(F[2]);
-      RA Bnew[3];
-      const bool fresh = u_pending;
-      if (fresh) bilinear(Bnew);
-      u_pending = false;
-      __syncthreads();
-      if (q < zp0 + 1) continue;  // output padded plane q - 1 needs planes q - 2 .. q
-      const int Zp = q - 1, Z = Zp - 1;  // unmapped fine plane
-      const int c = Z >> 1;
-      if (fresh) {  // c advanced: planes c - 1, c, c + 1
-        for (int a = 0; a < 3; ++a) {
-          Bm[a] = B0[a];
-          B0[a] = Bp[a];
-          Bp[a] = Bnew[a];
-        }
-      }
-      if ((Z & 1) && Zp + 1 < zp1) {  // the next output plane starts coarse plane c + 1
-        load_u(c + 2);
-        u_pending = true;
-      }
-      if (!active) continue;
-      const RA* Bn = (Z & 1) ? Bp : Bm;
-      const RA phi = F[1][3];
-      const RA g[3] = {(F[0][1] + RA(4) * F[1][1] + F[2][1]) * (kInvH / RA(72)),
-                       (F[0][2] + RA(4) * F[1][2] + F[2][2]) * (kInvH / RA(72)), (F[2][0] - F[0][0]) * (kInvH / RA(72))};
-      const RA inv = rcp_newton(sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + RA(1e-12));
-      const RA pp = phi * (RA(1) - phi);
-      for (int a = 0; a < 3; ++a) {
-        const RA uf = RA(0.75) * B0[a] + RA(0.25) * Bn[a];
-        G[fgrid_at(b, a, Xp, Yp, Zp)] = Enc<TP>::go(phi * uf + kac * (pp * g[a] * inv), 0.f, 1.f);
-      }
-    }
-  }
-}
-
-// phi_f' = phi_f - div_h G + M lap_h phi_f.  A workgroup of 256 threads
-// owns a tile of kFnTX x kFnTY fine columns and marches it over up to kHoZ
-// planes.  Per plane it stages phi and the three components of G with a
-// one-column halo in LDS (G from the padded grid, which already holds the
-// ghost fluxes; phi mirrored or wrapped), each thread filters its column in
-// x and y from LDS, and the filtered values of planes z-1, z, z+1 stay in
-// registers.
-__host__ __device__ inline int fine_phase_tiles(int nx, int ny, int nz) {
-  return ((2 * nx + kFnTX - 1) / kFnTX) * ((2 * ny + kFnTY - 1) / kFnTY) * ((2 * nz + kHoZ - 1) / kHoZ);
-}
-
-template <class PR>
-__global__ void __launch_bounds__(256) fine_phase_kernel(const BoxDesc* __restrict__ boxes, int box0, int parity) {
-  using TP = typename PR::TP;
-  using RA = TP;  // arithmetic: FP64 for FP64 storage, FP32 otherwise
-  __shared__ RA sG[3][kFnNP];
-  __shared__ RA sP[kFnNP];
-  const BoxDesc& b = boxes[box0 + blockIdx.y];
-  const int fx = 2 * b.nx, fy = 2 * b.ny, fz = 2 * b.nz;
-  const int ntx = (fx + kFnTX - 1) / kFnTX, nty = (fy + kFnTY - 1) / kFnTY;
-  const int tiles = ntx * nty * ((fz + kHoZ - 1) / kHoZ);
-  const gptr<const TP> fphi = (gptr<const TP>)b.fphi[parity];
-  const gptr<TP> fout = (gptr<TP>)b.fphi[1 - parity];
-  const gptr<const TP> G = (gptr<const TP>)b.fgrid;
-  const RA mob = static_cast<RA>(b.mobility);
-  constexpr RA kInvH = 2, kInvH2 = 4;
-  const int tid = threadIdx.x;
-  const int lx = tid % kFnTX, ly = tid / kFnTX;
-  for (int t = blockIdx.x; t < tiles; t += gridDim.x) {  // uniform over the workgroup
-    const int x0 = (t % ntx) * kFnTX, y0 = ((t / ntx) % nty) * kFnTY, z0 = (t / (ntx * nty)) * kHoZ;
-    const int z1 = min(z0 + kHoZ, fz);
-    const int X = x0 + lx, Y = y0 + ly;
-    const bool active = X < fx && Y < fy;
-    // staged elements of this thread (e = tid, tid + 256): mapped phi column,
-    // padded flux column, and the values of the next plane in registers
-    constexpr int kPer = (kFnNP + 255) / 256;
-    int64_t ecol[kPer], gcol[kPer];
-    for (int j = 0; j < kPer; ++j) {
-      const int e = min(tid + 256 * j, kFnNP - 1);
-      const int xe = x0 - 1 + e % kFnPX, ye = y0 - 1 + e / kFnPX;
-      ecol[j] = fine_at(b, map_axis(xe, fx, b.wall[0]), map_axis(ye, fy, b.wall[1]), 0);
-      // padded coordinates; columns past the last tile's edge are never used
-      gcol[j] = fgrid_at(b, 0, min(xe + 1, fx + 1), min(ye + 1, fy + 1), 0);
-    }
-    const int64_t fplane = static_cast<int64_t>(fx) * fy;
-    const int64_t gplane = static_cast<int64_t>(fx + 2) * (fy + 2), gcomp = gplane * (fz + 2);
-    TP nP[kPer], nG[3][kPer];
-    auto load = [&](int q) {
-      const int64_t zoff = map_axis(q, fz, b.wall[2]) * fplane, goff = (q + 1) * gplane;
-      for (int j = 0; j < kPer; ++j) {
-        nP[j] = fphi[ecol[j] + zoff];
-        for (int a = 0; a < 3; ++a) nG[a][j] = G[gcol[j] + a * gcomp + goff];
-      }
-    };
-    auto commit = [&]() {
-      for (int j = 0; j < kPer; ++j) {
-        const int e = tid + 256 * j;
-        if (e >= kFnNP) continue;
-        sP[e] = dec<RA>(nP[j], 0.f, 1.f);
-        for (int a = 0; a < 3; ++a) sG[a][e] = dec<RA>(nG[a][j], 0.f, 1.f);
-      }
-    };
-    // filtered values of the staged plane at this thread's column:
-    // v[0] = sum w cx Gx, v[1] = sum w cy Gy, v[2] = sum w Gz, v[3] = sum w phi
-    // (w = (1, 4, 1) x (1, 4, 1)), v[4] = phi at the column
-    auto filt = [&](RA v[5]) {
-      const int c0 = (ly + 1) * kFnPX + lx + 1;
-      RA hx = 0, hy = 0, hz = 0, L = 0;
+    // filtered values of the flux plane at the output column:
+    // v[0] = sum w cx Gx, v[1] = sum w cy Gy, v[2] = sum w Gz, w = (1, 4, 1) x (1, 4, 1)
+    auto filt_g = [&](RA v[3]) {
+      const int c0 = gy * kFsGX + gx;
+      RA hx = 0, hy = 0, hz = 0;
       for (int cy = -1; cy <= 1; ++cy)
         for (int cx = -1; cx <= 1; ++cx) {
           const RA w = (cx ? RA(1) : RA(4)) * (cy ? RA(1) : RA(4));
-          const int e = c0 + cy * kFnPX + cx;
+          const int e = c0 + cy * kFsGX + cx;
           if (cx) hx += w * RA(cx) * sG[0][e];
           if (cy) hy += w * RA(cy) * sG[1][e];
           hz += w * sG[2][e];
-          L += w * sP[e];
         }
       v[0] = hx;
       v[1] = hy;
       v[2] = hz;
-      v[3] = L;
-      v[4] = sP[c0];
     };
-    RA V[3][5] = {};
-    load(z0 - 1);
-    for (int q = z0 - 1; q <= z1; ++q) {
+    // bilinear sums of the coarse planes around the first flux plane
+    // (unmapped fine plane z0 - 1, coarse plane (z0 - 1) >> 1)
+    RA Bm[3], B0[3], Bp[3];
+    {
+      const int c0 = (z0 - 1) >> 1;
+      auto first = [&](int p, RA B[3]) {
+        load_u(p);
+        commit_u();
+        __syncthreads();
+        bilinear(B);
+        __syncthreads();
+      };
+      first(c0 - 1, Bm);
+      first(c0, B0);
+      first(c0 + 1, Bp);
+    }
+    bool u_pending = false;
+    RA F[4][4] = {}, V[3][3] = {};
+    load(z0 - 2);
+    for (int r = z0 - 2; r <= z1 + 1; ++r) {
       commit();
+      if (u_pending) commit_u();
       __syncthreads();
-      if (q < z1) load(q + 1);  // in flight while this plane is filtered and used
-      for (int k = 0; k < 5; ++k) {
+      if (r < z1 + 1) load(r + 1);  // in flight while this plane is filtered and used
+      for (int k = 0; k < 4; ++k) {
+        F[0][k] = F[1][k];
+        F[1][k] = F[2][k];
+        F[2][k] = F[3][k];
+      }
+      filt(F[3]);
+      RA Bnew[3];
+      const bool fresh = u_pending;
+      if (fresh) bilinear(Bnew);
+      u_pending = false;
+      if (r >= z0) {  // flux plane p = r - 1 from the filtered planes r - 2 .. r
+        const int p = r - 1, c = p >> 1;
+        if (fresh) {  // c advanced: planes c - 1, c, c + 1
+          for (int a = 0; a < 3; ++a) {
+            Bm[a] = B0[a];
+            B0[a] = Bp[a];
+            Bp[a] = Bnew[a];
+          }
+        }
+        if ((p & 1) && p + 1 <= z1) {  // the next flux plane starts coarse plane c + 1
+          load_u(c + 2);
+          u_pending = true;
+        }
+        const bool odd = (p & 1) != 0;
+        const RA phi = F[2][3];
+        const RA g[3] = {(F[1][1] + RA(4) * F[2][1] + F[3][1]) * (kInvH / RA(72)),
+                         (F[1][2] + RA(4) * F[2][2] + F[3][2]) * (kInvH / RA(72)),
+                         (F[3][0] - F[1][0]) * (kInvH / RA(72))};
+        const RA inv = rcp_newton(sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + RA(1e-12));
+        const RA pp = phi * (RA(1) - phi);
+        if (gthread)
+          for (int a = 0; a < 3; ++a) {
+            const RA uf = RA(0.75) * B0[a] + RA(0.25) * (odd ? Bp[a] : Bm[a]);
+            sG[a][tid] = phi * uf + kac * (pp * g[a] * inv);
+          }
+      }
+      __syncthreads();
+      if (r < z0) continue;
+      for (int k = 0; k < 3; ++k) {
         V[0][k] = V[1][k];
         V[1][k] = V[2][k];
       }
-      filt(V[2]);
-      __syncthreads();
-      if (q < z0 + 1 || !active) continue;  // output plane q - 1 needs planes q - 2 .. q
-      const int z = q - 1;
-      const RA phi = V[1][4];
+      if (inner) filt_g(V[2]);
+      if (r < z0 + 2 || !active) continue;  // output plane r - 2 needs flux planes r - 3 .. r - 1
+      const int z = r - 2;
+      const RA phi = F[1][3];
       const RA div = ((V[0][0] + RA(4) * V[1][0] + V[2][0]) + (V[0][1] + RA(4) * V[1][1] + V[2][1]) +
                       (V[2][2] - V[0][2])) * (kInvH / RA(72));
-      const RA lap = ((V[0][3] + RA(4) * V[1][3] + V[2][3]) * RA(1.0 / 36.0) - RA(6) * phi) * kInvH2;
+      const RA lap = ((F[0][0] + RA(4) * F[1][0] + F[2][0]) * RA(1.0 / 36.0) - RA(6) * phi) * kInvH2;
       fout[fine_at(b, X, Y, z)] = Enc<TP>::go(phi - div + mob * lap, 0.f, 1.f);
     }
   }
@@ -1309,14 +1252,11 @@ hipError_t launch_fine_get(int precision, const BoxDesc& box, int parity, double
   });
 }
 
-int fine_tiles(int nx, int ny, int nz, bool flux) {
-  return flux ? fine_flux_tiles(nx, ny, nz) : fine_phase_tiles(nx, ny, nz);
-}
+int fine_tiles(int nx, int ny, int nz) { return fine_step_tiles(nx, ny, nz); }
 
 hipError_t launch_fine_phase(int precision, bool gc, const BoxDesc* d_boxes, int box0, int nbox, int parity,
-                             int u_blocks, int flux_tiles, int phase_tiles, int restrict_blocks, hipStream_t stream) {
-  if (nbox <= 0 || u_blocks <= 0 || flux_tiles <= 0 || phase_tiles <= 0 || restrict_blocks <= 0)
-    return hipErrorInvalidValue;
+                             int u_blocks, int step_tiles, int restrict_blocks, hipStream_t stream) {
+  if (nbox <= 0 || u_blocks <= 0 || step_tiles <= 0 || restrict_blocks <= 0) return hipErrorInvalidValue;
   return dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
     if (gc)
@@ -1327,9 +1267,8 @@ hipError_t launch_fine_phase(int precision, bool gc, const BoxDesc* d_boxes, int
                          parity);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fine_flux_kernel<PR>), dim3(flux_tiles, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((fine_phase_kernel<PR>), dim3(phase_tiles, nbox), dim3(256), 0, stream, d_boxes, box0, parity);
+    hipLaunchKernelGGL((fine_step_kernel<PR>), dim3(step_tiles, nbox), dim3(kFsThreads), 0, stream, d_boxes, box0,
+                       parity);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((fine_restrict_kernel<PR>), dim3(restrict_blocks, nbox), dim3(256), 0, stream, d_boxes, box0,
                        1 - parity);

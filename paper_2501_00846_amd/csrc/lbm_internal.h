@@ -75,7 +75,7 @@ hipError_t launch_high_order_phase(int precision, bool gc, bool literal, const B
 int high_order_blocks_per_box(int64_t max_nodes);
 int high_order_phase_tiles(int nx, int ny, int nz);
 
-// Finer phase-field grid (LBM_FINE_PHASE), boxes with fphi / fgrid / aux
+// Finer phase-field grid (LBM_FINE_PHASE), boxes with fphi / aux
 // (3 planes) allocated.
 // launch_fine_init: fine phi of buffer `parity` interpolated from the coarse
 // phi, then the coarse phi replaced by the restriction (d_box: this box's
@@ -90,12 +90,12 @@ hipError_t launch_fine_get(int precision, const BoxDesc& box, int parity, double
 // - 1: reads level `parity` (coarse state and fine phi), writes the fine phi
 // of buffer 1 - parity and overwrites the coarse phi of buffer 1 - parity
 // with its restriction.  Runs after the fused step of the same parity.
-// u_blocks: high_order_blocks_per_box of the largest box; flux_tiles /
-// phase_tiles: the largest fine_tiles(..., true / false) over the boxes (one
-// workgroup per tile); restrict_blocks: workgroups per box of the restriction.
+// u_blocks: high_order_blocks_per_box of the largest box; step_tiles: the
+// largest fine_tiles over the boxes (one workgroup per tile);
+// restrict_blocks: workgroups per box of the restriction.
 hipError_t launch_fine_phase(int precision, bool gc, const BoxDesc* d_boxes, int box0, int nbox, int parity,
-                             int u_blocks, int flux_tiles, int phase_tiles, int restrict_blocks, hipStream_t stream);
-int fine_tiles(int nx, int ny, int nz, bool flux);
+                             int u_blocks, int step_tiles, int restrict_blocks, hipStream_t stream);
+int fine_tiles(int nx, int ny, int nz);
 
 constexpr int kDiagValues = 28;
 constexpr int kDiagBlocks = 1024;

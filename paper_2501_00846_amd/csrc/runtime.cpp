@@ -33,7 +33,6 @@ struct Box {
   void* mem[2] = {nullptr, nullptr};
   void* aux = nullptr;  // phi storage type; LBM_HIGH_ORDER_AC: 6 planes of n values; LBM_FINE_PHASE: 3
   void* fmem[2] = {nullptr, nullptr};  // LBM_FINE_PHASE: fine phi per parity
-  void* fgrid = nullptr;               // LBM_FINE_PHASE: fine flux (padded grid)
   int64_t n = 0;
   bool initialized = false;
   double enc_off[10] = {0};
@@ -52,8 +51,7 @@ struct lbm_ctx {
   int ho_tiles = 1; // workgroups per box of the fourth-order phase kernel (largest box)
   bool fine = false;   // LBM_FINE_PHASE (all boxes)
   int fine_u_bpb = 1;  // with LBM_FINE_PHASE: workgroups per box of the coarse velocity kernel,
-  int fine_ftiles = 1; // of the fine flux kernel (tiles of the largest box),
-  int fine_tiles = 1;  // of the fine phase kernel (tiles of the largest box)
+  int fine_tiles = 1;  // of the fine step kernel (tiles of the largest box)
   int fine_rbpb = 1;   // and of the restriction
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -237,7 +235,7 @@ hipError_t enqueue_steps(lbm_ctx* c, int nsteps, int parity0) {
     }
     if (c->fine) {
       e = lbm::launch_fine_phase(c->precision, c->gc, c->d_boxes, 0, static_cast<int>(c->boxes.size()), parity,
-                                 c->fine_u_bpb, c->fine_ftiles, c->fine_tiles, c->fine_rbpb, c->stream);
+                                 c->fine_u_bpb, c->fine_tiles, c->fine_rbpb, c->stream);
       if (e != hipSuccess) return e;
     }
     parity ^= 1;
@@ -487,20 +485,17 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
           lbm_destroy(c);
           return fail(nullptr, LBM_ERR_OOM, "lbm_create: high-order phase buffer allocation failed (box %d)", i);
         }
-        b.desc.aux = static_cast<double*>(b.aux);
+        b.desc.aux = b.aux;
       }
       if (c->fine) {
         const int64_t nf = 8 * b.n;
-        const int64_t np = static_cast<int64_t>(2 * b.prm.nx + 2) * (2 * b.prm.ny + 2) * (2 * b.prm.nz + 2);
         b.aux = dev_alloc(c, align256(lbm::phi_bytes(c->precision, 3 * b.n)));
-        b.fgrid = dev_alloc(c, align256(lbm::phi_bytes(c->precision, 3 * np)));
         for (int s = 0; s < 2; ++s) b.fmem[s] = dev_alloc(c, align256(lbm::phi_bytes(c->precision, nf)));
-        if (!b.aux || !b.fgrid || !b.fmem[0] || !b.fmem[1]) {
+        if (!b.aux || !b.fmem[0] || !b.fmem[1]) {
           lbm_destroy(c);
           return fail(nullptr, LBM_ERR_OOM, "lbm_create: fine phase-field buffer allocation failed (box %d)", i);
         }
-        b.desc.aux = static_cast<double*>(b.aux);
-        b.desc.fgrid = b.fgrid;
+        b.desc.aux = b.aux;
         for (int s = 0; s < 2; ++s) b.desc.fphi[s] = b.fmem[s];
       }
     }
@@ -514,8 +509,7 @@ lbm_status lbm_create(const lbm_params* boxes, int32_t n_boxes, const lbm_device
     if (c->fine) {
       c->fine_u_bpb = lbm::high_order_blocks_per_box(max_n);
       for (auto& b : c->boxes) {
-        c->fine_ftiles = std::max(c->fine_ftiles, lbm::fine_tiles(b.prm.nx, b.prm.ny, b.prm.nz, true));
-        c->fine_tiles = std::max(c->fine_tiles, lbm::fine_tiles(b.prm.nx, b.prm.ny, b.prm.nz, false));
+        c->fine_tiles = std::max(c->fine_tiles, lbm::fine_tiles(b.prm.nx, b.prm.ny, b.prm.nz));
       }
       c->fine_rbpb = static_cast<int>(std::min<int64_t>(4096, (max_n + 255) / 256));
     }
@@ -694,7 +688,7 @@ lbm_status lbm_step_unbatched(lbm_ctx* c, int32_t nsteps) {
                                                 c->parity, c->ho_bpb, c->ho_tiles, c->stream));
       if (c->fine)
         HIP_TRY(c, lbm::launch_fine_phase(c->precision, c->gc, c->d_boxes, static_cast<int>(k), 1, c->parity,
-                                          c->fine_u_bpb, c->fine_ftiles, c->fine_tiles, c->fine_rbpb, c->stream));
+                                          c->fine_u_bpb, c->fine_tiles, c->fine_rbpb, c->stream));
     }
     c->parity ^= 1;
   }
@@ -942,7 +936,6 @@ void lbm_destroy(lbm_ctx* c) {
     for (int s = 0; s < 2; ++s) dev_free(c, b.mem[s]);
     for (int s = 0; s < 2; ++s) dev_free(c, b.fmem[s]);
     dev_free(c, b.aux);
-    dev_free(c, b.fgrid);
   }
   dev_free(c, c->d_boxes);
   dev_free(c, c->d_items);

@@ -39,16 +39,14 @@ struct BoxDesc {
   int32_t zero_offsets;   // 1 if every enc_off is +0 (the default encoding)
   int32_t pitch;          // elements from one stored row to the next (>= nx; the
                           // padding after column nx-1 is never read or written)
-  double* aux;            // LBM_HIGH_ORDER_AC: 6 compact planes of nx*ny*nz doubles
-                          // (u, then phi (1 - phi) n4) of the step's level n;
-                          // LBM_FINE_PHASE: 3 such planes (u); else NULL
+  void* aux;              // LBM_HIGH_ORDER_AC: 6 compact planes of nx*ny*nz values
+                          // of the phi storage type (u, then phi (1 - phi) n4)
+                          // of the step's level n; LBM_FINE_PHASE: 3 such
+                          // planes (u); else NULL
   // LBM_FINE_PHASE: the phase field on the grid refined by 2 per axis,
-  // [2nz][2ny][2nx] (compact) of the phi storage type, per parity; and the
-  // fine flux of the step, 3 planes [3][2nz+2][2ny+2][2nx+2] of the phi
-  // storage type over the fine grid grown by one ghost layer on every side.
-  // NULL otherwise.
+  // [2nz][2ny][2nx] (compact) of the phi storage type, per parity; NULL
+  // otherwise.
   void* fphi[2];
-  void* fgrid;
 };
 
 // One unit of work of the fused step: an output tile (x0, y0) of one box,
