@@ -413,6 +413,9 @@ def precision_study(args):
 
 
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written
+# the calibration copy's kernel name; the run also launches torch's fill kernel
+# (torch.ones: nothing read, 1 GiB written), which must not enter the average
+COPY_KERNEL = "MulFunctor"
 
 
 def copy_calibration(reps):
@@ -531,7 +534,7 @@ def main():
     ap.add_argument("--copy-fetch-csv")
     ap.add_argument("--copy-write-csv")
     ap.add_argument("--valu-csv")
-    ap.add_argument("--copy-kernel", default="elementwise")
+    ap.add_argument("--copy-kernel", default=COPY_KERNEL)
     ap.add_argument("--closure", default="moment", choices=["moment", "gradient"],
                     help="a2 from the stored second moment (the paper's algorithm) or from the "
                          "velocity gradient (5-field state)")

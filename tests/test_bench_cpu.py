@@ -32,8 +32,11 @@ def test_traffic_key_names_workload_precision_and_launch():
 def test_counter_summary_scaling_and_lookup(tmp_path):
     """Counters of two dispatches (each split over two hardware instances) are
     averaged per dispatch and scaled by the copy calibration: the copy moves
-    COPY_BYTES each way, FETCH_SIZE reports 2/5 of it and WRITE_SIZE all of it,
-    so reads scale by 2.5 and writes by 1."""
+    COPY_BYTES each way, FETCH_SIZE reports half of it (128-byte requests
+    counted as 64 bytes) and WRITE_SIZE all of it, so reads scale by 2 and
+    writes by 1.  The calibration run's fill kernel (no reads, COPY_BYTES
+    written) must not enter the copy's average: the default --copy-kernel
+    matches the multiply kernel only."""
     kib = bench.COPY_BYTES / 1024.0
     fetch = tmp_path / "fetch.csv"
     write = tmp_path / "write.csv"
@@ -43,18 +46,21 @@ def test_counter_summary_scaling_and_lookup(tmp_path):
     _counter_csv(fetch, "FETCH_SIZE", [(1, k, 300.0), (1, k, 100.0), (2, k, 200.0), (2, k, 200.0),
                                        (3, "encode_kernel", 9e9)])
     _counter_csv(write, "WRITE_SIZE", [(1, k, 500.0), (2, k, 700.0)])
-    _counter_csv(cfetch, "FETCH_SIZE", [(7, "elementwise_kernel", 0.4 * kib)])
-    _counter_csv(cwrite, "WRITE_SIZE", [(7, "elementwise_kernel", kib)])
+    fill = "void at::native::vectorized_elementwise_kernel<4, at::native::FillFunctor<float>, ...>"
+    mul = "void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<float, float, float, " \
+          "at::native::binary_internal::MulFunctor<float> >, ...>"
+    _counter_csv(cfetch, "FETCH_SIZE", [(6, fill, 0.0), (7, mul, 0.5 * kib), (8, mul, 0.5 * kib)])
+    _counter_csv(cwrite, "WRITE_SIZE", [(6, fill, kib), (7, mul, kib), (8, mul, kib)])
     out = tmp_path / "traffic.json"
     args = argparse.Namespace(fetch_csv=str(fetch), write_csv=str(write), copy_fetch_csv=str(cfetch),
-                              copy_write_csv=str(cwrite), copy_kernel="elementwise", config="C1",
+                              copy_write_csv=str(cwrite), copy_kernel=bench.COPY_KERNEL, config="C1",
                               precision="fp64", closure="moment", tuning="18,14,8,0",
                               traffic_json=str(out))
     bench.summarize_counters(args)
     data = json.load(open(out))
     ent = data["C1/fp64@18,14,8"]
-    assert abs(ent["fetch_scale"] - 2.5) < 1e-12 and ent["write_scale"] == 1.0
-    expect = 400.0 * 1024 * 2.5 + 600.0 * 1024
+    assert abs(ent["fetch_scale"] - 2.0) < 1e-12 and ent["write_scale"] == 1.0
+    expect = 400.0 * 1024 * 2.0 + 600.0 * 1024
     assert abs(ent["bytes_per_launch"] - expect) < 1e-6
     assert ent["bytes_per_update_algorithmic"] == 176
     assert abs(ent["bytes_per_update_measured"] - expect / 32768) < 1e-9
