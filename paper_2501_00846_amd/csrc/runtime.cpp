@@ -879,7 +879,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, lbm_tuning* best) {
     for (size_t i = 0; i < cands.size(); ++i)
       if (cands[i].ms <= 1.05f * first) fin.push_back(i);
     // re-timings span at least ~25 ms each, so that small boxes are not
-    // judged on a few hundred microseconds of launches
+    // decided on a few hundred microseconds of launches
     const int n2 = std::min(4096, std::max(2 * steps, static_cast<int>(25.0f / std::max(first, 1e-4f)) + 1));
     for (int pass = 0; pass < 2 && fin.size() > 1; ++pass)
       for (size_t j = 0; j < fin.size(); ++j) {

@@ -69,7 +69,7 @@ def test_longest_column_fp64():
     ref = oracle_run_state(prob, state, 1)
     # P starts at zero and the x, y moments of this z-only flow are round-off:
     # each moment is a signed sum of populations of size max(|P|, |J|), so
-    # agreement is judged on that scale
+    # agreement is measured on that scale
     s_mom = max(np.abs(ref[1]).max(), np.abs(ref[2:5]).max())
     for k, name in enumerate(lbm.FIELDS):
         scale = np.abs(ref[k]).max() if k == 0 else max(np.abs(ref[k]).max(), s_mom)

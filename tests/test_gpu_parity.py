@@ -96,7 +96,7 @@ def test_largest_plane_fp64():
                            np.stack([ref["Q"][:, 0, 0], ref["Q"][:, 1, 1], ref["Q"][:, 2, 2],
                                      ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
     # each moment is a signed sum of populations of size max(|P|, |J|): FP64
-    # agreement is judged on that scale (some Q components are far smaller)
+    # agreement is measured on that scale (some Q components are far smaller)
     s_mom = max(np.abs(refa[1]).max(), np.abs(refa[2:5]).max())
     for kf in range(11):
         scale = np.abs(refa[kf]).max() if kf == 0 else max(np.abs(refa[kf]).max(), s_mom)
