@@ -251,6 +251,15 @@ lbm_status lbm_get_state_points(lbm_ctx* ctx, int32_t box, int64_t n, const int6
 lbm_status lbm_get_fine_phase(lbm_ctx* ctx, int32_t box, double* out);
 lbm_status lbm_set_fine_phase(lbm_ctx* ctx, int32_t box, const double* in);
 
+/* The fine phase field (decoded to FP64) at n chosen fine nodes of a box
+ * created with LBM_FINE_PHASE: node[j] is a flat fine index
+ * X + 2nx (Y + 2ny Z) in [0, 8 N), out[j] its value.  For spot checks of
+ * large boxes without copying the whole fine field.  Synchronises.
+ * LBM_ERR_ARG for an index out of range, LBM_ERR_STATE before the box holds
+ * a state, LBM_ERR_UNSUPPORTED for a box without the flag. */
+lbm_status lbm_get_fine_phase_points(lbm_ctx* ctx, int32_t box, int64_t n, const int64_t* node,
+                                     double* out);
+
 /* Offset-and-scale encoding of the 10 moments of one box in the 16-bit
  * storage modes: stored = (value - offset[k]) * scale[k], k over P, Jx, Jy, Jz,
  * Qxx, Qyy, Qzz, Qxy, Qxz, Qyz, computed in FP32 and rounded to nearest even.

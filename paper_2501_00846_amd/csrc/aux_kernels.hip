@@ -895,6 +895,16 @@ __global__ void fine_decode_kernel(BoxDesc b, int s, double* __restrict__ dst, i
     dst[i] = dec<double>(fphi[i], 0.f, 1.f);
 }
 
+template <class PR>
+__global__ void fine_gather_kernel(BoxDesc b, int s, const int64_t* __restrict__ idx, int64_t n,
+                                   double* __restrict__ out) {
+  using TP = typename PR::TP;
+  const gptr<const TP> fphi = (gptr<const TP>)b.fphi[s];
+  for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < n;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[j] = dec<double>(fphi[idx[j]], 0.f, 1.f);
+}
+
 // The fine step phi_f' = phi_f - div_h G + M lap_h phi_f, with the flux
 // G = phi u_f + (4M/W) phi (1 - phi) n computed where it is used.  A
 // workgroup of 512 threads owns a tile of kFsTX x kFsTY fine columns and
@@ -1248,6 +1258,16 @@ hipError_t launch_fine_get(int precision, const BoxDesc& box, int parity, double
   return dispatch(precision, [&](auto pr) {
     using PR = decltype(pr);
     hipLaunchKernelGGL((fine_decode_kernel<PR>), dim3(grid_for(nf, 256)), dim3(256), 0, stream, box, parity, d_dst, nf);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_fine_gather(int precision, const BoxDesc& box, int parity, const int64_t* d_idx, int64_t n,
+                              double* d_out, hipStream_t stream) {
+  return dispatch(precision, [&](auto pr) {
+    using PR = decltype(pr);
+    hipLaunchKernelGGL((fine_gather_kernel<PR>), dim3(grid_for(n, 256)), dim3(256), 0, stream, box, parity, d_idx, n,
+                       d_out);
     return hipGetLastError();
   });
 }

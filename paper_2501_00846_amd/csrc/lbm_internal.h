@@ -86,6 +86,10 @@ hipError_t launch_fine_init(int precision, const BoxDesc& box, const BoxDesc* d_
 hipError_t launch_fine_set(int precision, const BoxDesc& box, const BoxDesc* d_box, int parity, const double* d_src,
                            hipStream_t stream);
 hipError_t launch_fine_get(int precision, const BoxDesc& box, int parity, double* d_dst, hipStream_t stream);
+// launch_fine_gather: the decoded fine phi at n flat fine indices d_idx
+// (device, each in [0, 8 N)) into d_out.
+hipError_t launch_fine_gather(int precision, const BoxDesc& box, int parity, const int64_t* d_idx, int64_t n,
+                              double* d_out, hipStream_t stream);
 // The phase update of a step on the fine grids of boxes box0 .. box0 + nbox
 // - 1: reads level `parity` (coarse state and fine phi), writes the fine phi
 // of buffer 1 - parity and overwrites the coarse phi of buffer 1 - parity

@@ -598,6 +598,29 @@ lbm_status lbm_get_fine_phase(lbm_ctx* c, int32_t box, double* out) {
   return LBM_OK;
 }
 
+lbm_status lbm_get_fine_phase_points(lbm_ctx* c, int32_t box, int64_t n, const int64_t* node, double* out) {
+  lbm_status s = check_box(c, box);
+  if (s != LBM_OK) return s;
+  if (n < 0 || (n > 0 && (!node || !out)))
+    return fail(c, LBM_ERR_ARG, "lbm_get_fine_phase_points: bad n / NULL arrays");
+  if (!c->fine) return fail(c, LBM_ERR_UNSUPPORTED, "lbm_get_fine_phase_points: the context has no LBM_FINE_PHASE");
+  Box& b = c->boxes[box];
+  if (!b.initialized) return fail(c, LBM_ERR_STATE, "lbm_get_fine_phase_points: box %d not initialised", box);
+  for (int64_t j = 0; j < n; ++j)
+    if (node[j] < 0 || node[j] >= 8 * b.n)
+      return fail(c, LBM_ERR_ARG, "lbm_get_fine_phase_points: node[%lld] out of range", static_cast<long long>(j));
+  if (n == 0) return LBM_OK;
+  // staging: n indices (as doubles' storage) + n values
+  if ((s = ensure_stage(c, 2 * n)) != LBM_OK) return s;
+  int64_t* d_idx = reinterpret_cast<int64_t*>(c->d_stage);
+  double* d_out = c->d_stage + n;
+  HIP_TRY(c, hipMemcpyAsync(d_idx, node, n * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, lbm::launch_fine_gather(c->precision, b.desc, c->parity, d_idx, n, d_out, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(out, d_out, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
 lbm_status lbm_set_fine_phase(lbm_ctx* c, int32_t box, const double* in) {
   lbm_status s = check_box(c, box);
   if (s != LBM_OK) return s;

@@ -91,6 +91,8 @@ _SIGS = {
     "lbm_set_fine_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "lbm_get_state_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_get_fine_phase_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                                 ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_set_encoding": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "lbm_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(lbm_tuning)]),
@@ -234,6 +236,13 @@ def lbm_get_fine_phase(ctx, box, n):
 
 def lbm_set_fine_phase(ctx, box, n, phif):
     _check(load_library().lbm_set_fine_phase(ctx, box, _ptr(_f64(phif, 8 * n))), ctx)
+
+
+def lbm_get_fine_phase_points(ctx, box, nodes):
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.empty(nodes.size)
+    _check(load_library().lbm_get_fine_phase_points(ctx, box, nodes.size, _ptr(nodes), _ptr(out)), ctx)
+    return out
 
 
 def lbm_get_state_points(ctx, box, nodes):
@@ -385,6 +394,13 @@ class Context:
         """The fine phase field (LBM_FINE_PHASE) as (2nz, 2ny, 2nx)."""
         p = self.problems[box]
         return lbm_get_fine_phase(self.ctx, box, self.sizes[box]).reshape(2 * p.nz, 2 * p.ny, 2 * p.nx)
+
+    def fine_phase_at(self, box, points):
+        """Fine phi at fine nodes (X, Y, Z) -> (n,)."""
+        p = self.problems[box]
+        pts = np.asarray(points, dtype=np.int64).reshape(-1, 3)
+        nodes = pts[:, 0] + 2 * p.nx * (pts[:, 1] + 2 * p.ny * pts[:, 2])
+        return lbm_get_fine_phase_points(self.ctx, box, nodes)
 
     def set_fine_phase(self, box, phif):
         lbm_set_fine_phase(self.ctx, box, self.sizes[box], phif)

@@ -94,6 +94,7 @@ def test_null_context_calls_fail_cleanly():
     assert lib.lbm_get_fields(None, 0, None, None, None, None) == -1
     assert lib.lbm_get_fine_phase(None, 0, None) == -1
     assert lib.lbm_set_fine_phase(None, 0, None) == -1
+    assert lib.lbm_get_fine_phase_points(None, 0, 0, None, None) == -1
     assert lib.lbm_bytes_per_update(None) == 0.0
     assert lib.lbm_total_nodes(None) == 0
     lib.lbm_destroy(None)

@@ -235,3 +235,33 @@ def test_unbatched_steps_equal_batched_steps():
     for i in range(2):
         assert np.array_equal(out[0][i][0], out[1][i][0]), i
         assert np.array_equal(out[0][i][1], out[1][i][1]), i
+
+
+def test_sampled_fine_values_equal_the_whole_field():
+    """lbm_get_fine_phase_points returns the decoded fine phi at chosen fine
+    nodes (corners, faces, random) bitwise equal to the whole-field readback,
+    in FP64 and FP32; an index out of range is refused, and a context without
+    the flag reports LBM_ERR_UNSUPPORTED."""
+    for precision in ("fp64", "fp32"):
+        prob = _prob((17, 9, 7), (W_, P_, W_))
+        state = smooth_random_state(prob, seed=91)
+        with lbm.Context(prob, precision) as ctx:
+            ctx.set_state(0, state.reshape(-1))
+            ctx.step(2)
+            whole = ctx.get_fine_phase(0)
+            fz, fy, fx = whole.shape
+            rng = np.random.default_rng(92)
+            pts = [(0, 0, 0), (fx - 1, fy - 1, fz - 1), (fx - 1, 0, fz // 2), (0, fy - 1, 1)]
+            pts += [tuple(int(v) for v in (rng.integers(fx), rng.integers(fy), rng.integers(fz))) for _ in range(40)]
+            got = ctx.fine_phase_at(0, pts)
+            expect = np.array([whole[z, y, x] for x, y, z in pts])
+            assert np.array_equal(got, expect), precision
+            with pytest.raises(lbm.LbmError) as err:
+                lbm.lbm_get_fine_phase_points(ctx.ctx, 0, np.array([fx * fy * fz], dtype=np.int64))
+            assert err.value.status == -1  # LBM_ERR_ARG
+    plain = _prob((8, 6, 5), (P_, P_, P_), fine_phase=False)
+    with lbm.Context(plain, "fp64") as ctx:
+        ctx.set_state(0, smooth_random_state(plain, seed=93).reshape(-1))
+        with pytest.raises(lbm.LbmError) as err:
+            ctx.fine_phase_at(0, [(0, 0, 0)])
+        assert err.value.status == -2  # LBM_ERR_UNSUPPORTED

@@ -302,9 +302,10 @@ def test_drop_into_pool_512_fine_phase_one_step(precision):
     nodes), in both modes the benchmark times: from the seeded initial
     fields (the fine phi their interpolation, the coarse phi its restriction)
     one step, checked at sampled coarse nodes against the per-node fine
-    oracle: the flow part, and the new coarse phi, the mean of the 8 updated
-    fine nodes of the cell.  Reduced precision: the fine and coarse phi the
-    oracle starts from are rounded to FP32 like the stored ones."""
+    oracle: the flow part, the new coarse phi (the mean of the 8 updated fine
+    nodes of the cell), and those 8 fine nodes themselves.  Reduced
+    precision: the fine and coarse phi the oracle starts from are rounded to
+    FP32 like the stored ones."""
     case = workloads.drop_into_pool()
     case.problem.fine_phase = True
     prob = case.problem
@@ -318,6 +319,9 @@ def test_drop_into_pool_512_fine_phase_one_step(precision):
         _log("tuning %s" % ctx.tuning())
         ctx.step(1)
         got = ctx.state_at(0, pts)
+        kids = [(2 * x + dx, 2 * y + dy, 2 * z + dz) for x, y, z in pts for dz in (0, 1) for dy in (0, 1)
+                for dx in (0, 1)]
+        got_fine = ctx.fine_phase_at(0, kids)
     rnd = (lambda v: float(v)) if precision == "fp64" else (lambda v: float(np.float32(v)))
     phi0 = quantize(case.phi, precision, 0)
     cache = {}
@@ -337,6 +341,13 @@ def test_drop_into_pool_512_fine_phase_one_step(precision):
                                      ref["Q"][:, 0, 1], ref["Q"][:, 0, 2], ref["Q"][:, 1, 2]])])
     force = None if precision == "fp64" else force_scale(prob, st.phi, q(case.pstar, 1), pts)
     _compare(got, refa, precision, force)
+    # the fine nodes themselves: the 8 children of every sampled coarse node
+    po = PW.FinePointOracle(st, fine0, prob)
+    ref_fine = np.array([po.phase_at(*k) for k in kids])
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    err = np.abs(got_fine - ref_fine).max()
+    _log("  fine phi at %d fine nodes: max err %.3e" % (len(kids), err))
+    assert err <= tol * np.abs(ref_fine).max(), err
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16_os"])
