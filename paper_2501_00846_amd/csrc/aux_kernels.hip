@@ -985,14 +985,16 @@ __global__ void __launch_bounds__(kFsThreads) fine_step_kernel(const BoxDesc* __
       const int xe = x0 - 2 + e % kFsPX, ye = y0 - 2 + e / kFsPX;
       ecol[j] = fine_at(b, map_axis(xe, fx, b.wall[0]), map_axis(ye, fy, b.wall[1]), 0);
     }
-    TP next[kPer];
-    auto load = [&](int r) {  // unmapped fine plane r, continued
+    // staged values of a plane in registers: two buffers, the even and the
+    // odd planes of the march, each loaded two planes before it is staged
+    TP bufA[kPer], bufB[kPer];
+    auto load = [&](int r, TP* buf) {  // unmapped fine plane r, continued
       const int64_t zoff = map_axis(r, fz, b.wall[2]) * fplane;
-      for (int j = 0; j < kPer; ++j) next[j] = fphi[ecol[j] + zoff];
+      for (int j = 0; j < kPer; ++j) buf[j] = fphi[ecol[j] + zoff];
     };
-    auto commit = [&]() {
+    auto commit = [&](const TP* buf) {
       for (int j = 0; j < kPer; ++j)
-        if (tid + kFsThreads * j < kFsPN) sP[tid + kFsThreads * j] = dec<RA>(next[j], 0.f, 1.f);
+        if (tid + kFsThreads * j < kFsPN) sP[tid + kFsThreads * j] = dec<RA>(buf[j], 0.f, 1.f);
     };
     // velocity staging: coarse columns [cx0, cx0 + kFsUX) x [cy0, cy0 + kFsUY),
     // this thread's elements, their physical columns and the signs of the odd
@@ -1085,12 +1087,13 @@ __global__ void __launch_bounds__(kFsThreads) fine_step_kernel(const BoxDesc* __
     }
     bool u_pending = false;
     RA F[4][4] = {}, V[3][3] = {};
-    load(z0 - 2);
-    for (int r = z0 - 2; r <= z1 + 1; ++r) {
-      commit();
+    // one staged plane r: its values come from buf, which then takes plane
+    // r + 2 (in flight while this plane and the next are filtered and used)
+    auto plane = [&](int r, TP* buf) {
+      commit(buf);
       if (u_pending) commit_u();
       __syncthreads();
-      if (r < z1 + 1) load(r + 1);  // in flight while this plane is filtered and used
+      if (r + 2 <= z1 + 1) load(r + 2, buf);
       for (int k = 0; k < 4; ++k) {
         F[0][k] = F[1][k];
         F[1][k] = F[2][k];
@@ -1128,19 +1131,26 @@ __global__ void __launch_bounds__(kFsThreads) fine_step_kernel(const BoxDesc* __
           }
       }
       __syncthreads();
-      if (r < z0) continue;
+      if (r < z0) return;
       for (int k = 0; k < 3; ++k) {
         V[0][k] = V[1][k];
         V[1][k] = V[2][k];
       }
       if (inner) filt_g(V[2]);
-      if (r < z0 + 2 || !active) continue;  // output plane r - 2 needs flux planes r - 3 .. r - 1
+      if (r < z0 + 2 || !active) return;  // output plane r - 2 needs flux planes r - 3 .. r - 1
       const int z = r - 2;
       const RA phi = F[1][3];
       const RA div = ((V[0][0] + RA(4) * V[1][0] + V[2][0]) + (V[0][1] + RA(4) * V[1][1] + V[2][1]) +
                       (V[2][2] - V[0][2])) * (kInvH / RA(72));
       const RA lap = ((F[0][0] + RA(4) * F[1][0] + F[2][0]) * RA(1.0 / 36.0) - RA(6) * phi) * kInvH2;
       fout[fine_at(b, X, Y, z)] = Enc<TP>::go(phi - div + mob * lap, 0.f, 1.f);
+    };
+    // staged planes z0 - 2 .. z1 + 1 (at least 4), two per trip
+    load(z0 - 2, bufA);
+    load(z0 - 1, bufB);
+    for (int r = z0 - 2; r <= z1 + 1; r += 2) {
+      plane(r, bufA);
+      if (r + 1 <= z1 + 1) plane(r + 1, bufB);
     }
   }
 }
